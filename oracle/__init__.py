@@ -1,0 +1,156 @@
+"""CPU FP64 oracle (ctypes wrapper around ``pdf_oracle.c``).
+
+TEST INFRASTRUCTURE.  Only the tests, the package smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with
+the GPU library; it is compiled from its own C source with gcc.
+
+Functions follow the method of PDFFlow (arXiv:2012.08221): batched PDF
+evaluation over independent points (Sec. 2.1), alpha_s by the same 1-D
+interpolation (Sec. 2.1), and the luminosity part of the Monte Carlo integrand
+of Eq. (1) (Sec. 3.1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pdf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math: IEEE FP64)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                        "-ffp-contract=off", "-o", tmp, _SRC, "-lm", "-lpthread"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        d, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_long
+        _lib.ora_xfx.argtypes = [i32, d, i32, d, i32, d, d, d, i32, d, i64, d, d, d, i32, i32]
+        _lib.ora_locate.argtypes = [i32, d, i32, d, d, i64, d, d, d, d, d, d]
+        _lib.ora_stencil_absmax.argtypes = [i32, d, i32, d, i32, d, d, d, i32, d, i64, d, d, d]
+        _lib.ora_alphas.argtypes = [i32, d, d, i64, d, d, i32, i32]
+        _lib.ora_dy.argtypes = [i32, d, i32, d, i32, d, d, d, i32, d, d, i64, d, d,
+                                ctypes.c_double, ctypes.c_double, d, i32]
+        _lib.ora_hermite_basis.argtypes = [ctypes.c_double, d]
+        _lib.ora_hermite_eval.argtypes = [ctypes.c_double] * 7
+        _lib.ora_hermite_eval.restype = ctypes.c_double
+        _lib.ora_hermite_1d.argtypes = [d, d, ctypes.c_long, i32, i32, ctypes.c_double]
+        _lib.ora_hermite_1d.restype = ctypes.c_double
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def default_threads() -> int:
+    n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def xfx(grid, pids, x, q2, mode: int = 0, nthreads: int | None = None) -> np.ndarray:
+    """xf for pids (request order = column order) at points (x, q2) -> [n, len(pids)].
+
+    ``grid`` is any object with pids, x, q2, q_off, xf arrays (FP64 values).
+    mode 0: NaN outside the grid; mode 1: clamp to the grid edge.
+    """
+    lib = _load()
+    gp, gx, gq, go, gv = _i32(grid.pids), _f64(grid.x), _f64(grid.q2), _i32(grid.q_off), _f64(grid.xf)
+    rp = _i32(np.atleast_1d(pids))
+    x, q2 = _f64(x), _f64(q2)
+    n = x.shape[0]
+    out = np.empty((n, rp.shape[0]), dtype=np.float64)
+    lib.ora_xfx(gp.shape[0], _p(gp), gx.shape[0], _p(gx), go.shape[0] - 1, _p(go), _p(gq), _p(gv),
+                rp.shape[0], _p(rp), n, _p(x), _p(q2), _p(out), mode,
+                nthreads or default_threads())
+    return out
+
+
+def locate(grid, x, q2):
+    """(ix, s, iq, inside) per point: x interval, subgrid, subgrid-local Q^2 interval."""
+    lib = _load()
+    gx, gq, go = _f64(grid.x), _f64(grid.q2), _i32(grid.q_off)
+    x, q2 = _f64(x), _f64(q2)
+    n = x.shape[0]
+    ix, s, iq, ins = (np.empty(n, dtype=np.int32) for _ in range(4))
+    lib.ora_locate(gx.shape[0], _p(gx), go.shape[0] - 1, _p(go), _p(gq), n, _p(x), _p(q2),
+                   _p(ix), _p(s), _p(iq), _p(ins))
+    return ix, s, iq, ins.astype(bool)
+
+
+def stencil_absmax(grid, pids, x, q2) -> np.ndarray:
+    """max |knot value| over each point's stencil, per requested pid -> [n, len(pids)]."""
+    lib = _load()
+    gp, gx, gq, go, gv = _i32(grid.pids), _f64(grid.x), _f64(grid.q2), _i32(grid.q_off), _f64(grid.xf)
+    rp = _i32(np.atleast_1d(pids))
+    x, q2 = _f64(x), _f64(q2)
+    n = x.shape[0]
+    out = np.empty((n, rp.shape[0]), dtype=np.float64)
+    lib.ora_stencil_absmax(gp.shape[0], _p(gp), gx.shape[0], _p(gx), go.shape[0] - 1, _p(go),
+                           _p(gq), _p(gv), rp.shape[0], _p(rp), n, _p(x), _p(q2), _p(out))
+    return out
+
+
+def alphas(as_q2, as_val, q2, mode: int = 0, nthreads: int | None = None) -> np.ndarray:
+    lib = _load()
+    aq, av, q2 = _f64(as_q2), _f64(as_val), _f64(q2)
+    out = np.empty(q2.shape[0], dtype=np.float64)
+    lib.ora_alphas(aq.shape[0], _p(aq), _p(av), q2.shape[0], _p(q2), _p(out), mode,
+                   nthreads or default_threads())
+    return out
+
+
+def dy(grid, u1, u2, xmin: float, s: float, nthreads: int | None = None) -> np.ndarray:
+    """Per-point LO Drell-Yan-like integrand I(u1, u2) (see pdf_oracle.c)."""
+    lib = _load()
+    gp, gx, gq, go, gv = _i32(grid.pids), _f64(grid.x), _f64(grid.q2), _i32(grid.q_off), _f64(grid.xf)
+    aq, av = _f64(grid.as_q2), _f64(grid.as_val)
+    u1, u2 = _f64(u1), _f64(u2)
+    out = np.empty(u1.shape[0], dtype=np.float64)
+    lib.ora_dy(gp.shape[0], _p(gp), gx.shape[0], _p(gx), go.shape[0] - 1, _p(go), _p(gq), _p(gv),
+               aq.shape[0], _p(aq), _p(av), u1.shape[0], _p(u1), _p(u2), xmin, s, _p(out),
+               nthreads or default_threads())
+    return out
+
+
+def hermite_basis(t: float) -> np.ndarray:
+    h = np.empty(4, dtype=np.float64)
+    _load().ora_hermite_basis(t, _p(h))
+    return h
+
+
+def hermite_eval(z0, z1, y0, y1, m0, m1, z) -> float:
+    return _load().ora_hermite_eval(z0, z1, y0, y1, m0, m1, z)
+
+
+def hermite_1d(z, y, i: int, zq: float) -> float:
+    """1-D interpolant of knots (z, y) with the method's finite-difference slopes."""
+    z, y = _f64(z), _f64(y)
+    return _load().ora_hermite_1d(_p(z), _p(y), 1, z.shape[0], i, zq)
