@@ -1,0 +1,212 @@
+/*
+ * pdfx: batched parton-density and alpha_s interpolation on AMD MI355X (gfx950).
+ *
+ * The problem statement follows PDFFlow (arXiv:2012.08221), Sec. 2.1: a query
+ * is a set of flavours {a} plus two arrays of equal length, momentum fractions
+ * x_i and scales Q_i, and the answer is the array of interpolated values; the
+ * interpolation is the LHAPDF one, i.e. log-bicubic (cubic Hermite in ln x and
+ * in ln Q^2, finite-difference slopes) inside the Q^2 subgrid that holds the
+ * point, subgrids meeting at the flavour thresholds.  alpha_s(Q^2) is the same
+ * 1-D cubic Hermite in ln Q^2 (Sec. 2.1, last paragraph before Fig. 1).  The
+ * returned PDF quantity is x f(x, Q^2) (Sec. 3.2 divides the luminosity by x1 x2).
+ *
+ * Conventions for every call:
+ *  - All functions return PDFX_OK (0) or a negative pdfx_status.  Only errors
+ *    the host can see are returned; pdfx_last_error() gives a thread-local
+ *    message for the last failure on the calling thread.
+ *  - Device pointers are plain HIP device addresses on the current device
+ *    (e.g. torch tensor data pointers), contiguous, at least 8-byte aligned.
+ *    The caller owns them and the stream; the library never frees them.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every eval call
+ *    only enqueues work on it and returns; nothing is copied to or from the
+ *    host on the eval path.
+ *  - A failed call leaves every handle valid and enqueues nothing.
+ *  - PDG ids: 21 and 0 both mean the gluon; a pid absent from the grid
+ *    evaluates to 0; output columns follow the request order.
+ *  - Points outside the grid: PDFX_DOMAIN_NAN writes NaN for every column of
+ *    that point and counts the point (pdfx_domain_errors); PDFX_DOMAIN_CLAMP
+ *    evaluates at the point clamped to the grid edge (and counts nothing,
+ *    except NaN inputs, which give NaN and are counted in both modes).
+ *  - Ties: a Q^2 equal to a subgrid threshold uses the upper subgrid; a
+ *    query on the last knot of an axis uses the last interval.
+ */
+#ifndef PDFX_H
+#define PDFX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdfx_grid pdfx_grid; /* one PDF member, geometry + alpha_s on the device */
+typedef struct pdfx_set pdfx_set;   /* many members with uneven grids */
+
+/* Host description of one member.  Read only during pdfx_load_grid /
+ * pdfx_load_set; the caller may free it afterwards. */
+typedef struct pdfx_grid_desc {
+    int32_t n_flav;        /* number of parton rows, 1..64 */
+    const int32_t *pids;   /* [n_flav] PDG ids of the rows, distinct (0 and 21 count as equal) */
+    int32_t n_x;           /* number of x knots, 2..4096 */
+    const double *x;       /* [n_x] strictly increasing, x[0] > 0 */
+    int32_t n_sub;         /* number of Q^2 subgrids, 1..16 */
+    const int32_t *q_off;  /* [n_sub+1] offsets into q2; q_off[0] = 0, >= 2 knots per subgrid */
+    const double *q2;      /* [q_off[n_sub]] GeV^2, > 0; strictly increasing inside each
+                              subgrid; the last knot of subgrid s equals the first of s+1 */
+    const double *xf;      /* [n_flav][n_x][n_q] host values of x f, finite; NULL = none
+                              (then values must be passed to each eval call) */
+    int32_t n_as;          /* alpha_s knots (0 = none) */
+    const double *as_q2;   /* [n_as] non-decreasing; a repeated knot splits subgrids */
+    const double *as_val;  /* [n_as] alpha_s at the knots, finite */
+} pdfx_grid_desc;
+
+enum pdfx_status {
+    PDFX_OK = 0,
+    PDFX_EINVAL = -1,     /* invalid argument or descriptor */
+    PDFX_ENOMEM = -2,     /* device allocation failed */
+    PDFX_EHIP = -3,       /* a HIP runtime call failed */
+    PDFX_ENOALPHAS = -5,  /* the grid has no alpha_s knots */
+    PDFX_ENOVALUES = -6   /* no owned values and none passed */
+};
+
+/* Arithmetic of an evaluation.
+ * PDFX_F64:  everything in FP64; values, outputs FP64.
+ * PDFX_F32S: logs, knot search, subgrid choice and the local coordinate t in
+ *            FP64; t rounded to FP32; basis, slope folding, weights, stencil
+ *            FMAs, values and outputs FP32. */
+enum pdfx_prec { PDFX_F64 = 0, PDFX_F32S = 1 };
+
+enum pdfx_domain { PDFX_DOMAIN_NAN = 0, PDFX_DOMAIN_CLAMP = 1 };
+
+/* Maximum number of requested pids in one call. */
+#define PDFX_MAX_REQ 64
+
+/* ---- grid lifetime (Sec. 2.1: mkPDF builds a PDF object for one member) ---- */
+
+/* Validates d, derives per-interval tables on the host in FP64 and copies
+ * geometry, alpha_s knots and (if d->xf) FP64 and FP32 copies of the values to
+ * the current device.  Synchronous.  *out receives the handle. */
+int pdfx_load_grid(const pdfx_grid_desc *d, pdfx_grid **out);
+void pdfx_free_grid(pdfx_grid *g);
+
+/* Shape of a loaded grid (any pointer may be NULL). */
+int pdfx_grid_shape(const pdfx_grid *g, int32_t *n_flav, int32_t *n_x, int32_t *n_q,
+                    int32_t *n_sub, int32_t *n_as);
+
+/* ---- PDF evaluation (Sec. 2.1: py_xfxQ / xfxQ2 over arrays of points) ---- */
+
+/* out[p][r] = x f_{pids[r]}(x[p], q2[p]) for p < n_pts, r < n_req.
+ *  xf_dev   device values [n_flav][n_x][n_q] of the precision's type (FP64 for
+ *           PDFX_F64, FP32 for PDFX_F32S), or NULL to use the owned values.
+ *  pids     host array [n_req], 1 <= n_req <= PDFX_MAX_REQ.
+ *  x, q2    device FP64 [n_pts]; Q^2 in GeV^2.
+ *  out      device [n_pts][n_req], FP64 or FP32 by precision.
+ * n_pts = 0 is a no-op. */
+int pdfx_eval_xfx(const pdfx_grid *g, const void *xf_dev, int prec,
+                  const int32_t *pids, int32_t n_req,
+                  const double *x, const double *q2, int64_t n_pts,
+                  void *out, int domain_mode, void *stream);
+
+/* Same with Q instead of Q^2: Q^2 = Q*Q is formed in FP64 on the device. */
+int pdfx_eval_xfxQ(const pdfx_grid *g, const void *xf_dev, int prec,
+                   const int32_t *pids, int32_t n_req,
+                   const double *x, const double *q, int64_t n_pts,
+                   void *out, int domain_mode, void *stream);
+
+/* ---- alpha_s (Sec. 2.1, alpha_s paragraph; Fig. 1 py_alphasQ) ---- */
+
+/* out[p] = alpha_s(q2[p]) by 1-D cubic Hermite in ln Q^2 over the alpha_s
+ * knots, subgrids split at repeated knots.  q2 device FP64 [n]; out device
+ * FP64 (PDFX_F64) or FP32 (PDFX_F32S).  PDFX_ENOALPHAS if the grid has none. */
+int pdfx_eval_alphas(const pdfx_grid *g, const double *q2, int64_t n, void *out,
+                     int prec, int domain_mode, void *stream);
+
+/* ---- adjoint (derivative of the Sec. 2.1 map; used for differentiable fits) ----
+ * For a scalar L with dL/dout = grad_out ([n_pts][n_req], precision's type):
+ *  grad_xf  device [n_flav][n_x][n_q] of the precision's type, ACCUMULATED:
+ *           grad_xf[f][i][k] += sum_{p,r: row(r)=f} grad_out[p][r] * dout[p][r]/dv[f][i][k];
+ *           summed in FP64 on the device, then added; NULL = skip.
+ *  grad_x, grad_q2  device FP64 [n_pts], OVERWRITTEN with
+ *           sum_r grad_out[p][r] * dout[p][r]/dx (resp. /dQ^2); NULL = skip.
+ * Points outside the grid (NaN mode) contribute nothing and get NaN in
+ * grad_x/grad_q2; in CLAMP mode the derivative along a clamped axis is 0.
+ * The knot gradient uses device atomics: results are reproducible up to the
+ * FP64 summation order. */
+int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
+                           const int32_t *pids, int32_t n_req,
+                           const double *x, const double *q2, int64_t n_pts,
+                           const void *grad_out, void *grad_xf,
+                           double *grad_x, double *grad_q2,
+                           int domain_mode, void *stream);
+
+/* ---- many members in one launch (PDF sets are collections of members, Sec. 1) ---- */
+
+/* Loads n_mem members (each desc must carry values; grids may differ). */
+int pdfx_load_set(const pdfx_grid_desc *members, int32_t n_mem, pdfx_set **out);
+void pdfx_free_set(pdfx_set *s);
+
+/* out[m][p][r] = x f^{(m)}_{pids[r]}(x[p], q2[p]) for every member m, in one
+ * persistent launch that walks a (point tile, member) work list.  x, q2 device
+ * FP64 [n_pts] shared by all members; out device [n_mem][n_pts][n_req] FP64
+ * or FP32 by precision. */
+int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t n_req,
+                      const double *x, const double *q2, int64_t n_pts,
+                      void *out, int domain_mode, void *stream);
+
+/* ---- Monte Carlo luminosity integrand (Sec. 3.1, Eq. 1 with a unit matrix element) ----
+ * Per point p: x_j = exp(ln xmin + u_j[p] ln(1/xmin)) for j = 1,2;
+ * Q^2 = x1 x2 s clipped to the grid's Q^2 range;
+ * I[p] = (ln(1/xmin))^2 alpha_s(Q^2) sum_{q=1..5} xf_q(x1) xf_{-q}(x2),
+ * the log-map Jacobian x1 x2 (ln(1/xmin))^2 cancelling the 1/(x1 x2) of f = xf/x.
+ *  u1, u2   device FP64 [n] in [0,1).
+ *  out      device [n] FP64 or FP32 by precision (NULL = skip).
+ *  block_sums device FP64 [*n_blocks] partial sums of I (NULL = skip); the
+ *           call writes the number of partial sums it produces to *n_blocks
+ *           if n_blocks is non-NULL (query with n = 0 first to size it:
+ *           it is at most pdfx_dy_max_blocks()).
+ * Requires the grid's alpha_s knots and owned values (or xf_dev). */
+int pdfx_eval_dy(const pdfx_grid *g, const void *xf_dev, int prec,
+                 const double *u1, const double *u2, int64_t n,
+                 double xmin, double s, void *out, double *block_sums,
+                 int32_t *n_blocks, void *stream);
+int32_t pdfx_dy_max_blocks(void);
+
+/* Backward of sum_p I[p] with respect to the PDF knot values:
+ * grad_xf (device [n_flav][n_x][n_q], precision's type) += d(sum_p I[p]) / dv,
+ * scaled by `scale` (e.g. 1/n for a mean).  alpha_s knots are not differentiated. */
+int pdfx_eval_dy_backward(const pdfx_grid *g, const void *xf_dev, int prec,
+                          const double *u1, const double *u2, int64_t n,
+                          double xmin, double s, double scale, void *grad_xf,
+                          void *stream);
+
+/* ---- launch tuning ---- */
+
+/* Times the compiled launch shapes of pdfx_eval_xfx (prec, n_req, n_pts) on
+ * scratch buffers and keeps the fastest for this grid; with a non-NULL path
+ * the choice is also stored in / read from a JSON cache keyed by device,
+ * compute-unit count, grid signature, precision and size class.  Synchronous. */
+int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pts, const char *cache_path);
+int pdfx_autotune_set(pdfx_set *s, int prec, int32_t n_req, int64_t n_pts, const char *cache_path);
+
+/* Current launch shape of a grid: workgroup size and points per thread. */
+int pdfx_get_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
+/* Forces a launch shape (must be one of the compiled ones). */
+int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
+
+/* ---- diagnostics ---- */
+
+/* Number of out-of-grid points counted since the last call, over all eval
+ * calls on g; synchronises the device, then resets the counter. */
+int pdfx_domain_errors(const pdfx_grid *g, int64_t *count);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *pdfx_last_error(void);
+
+/* Library version string. */
+const char *pdfx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDFX_H */

@@ -1,0 +1,144 @@
+"""torch-facing API, named after the paper's interface (Sec. 2.1, Fig. 1):
+``mkPDF`` builds a PDF object for one member; ``xfxQ2`` / ``xfxQ`` /
+``py_xfxQ`` evaluate x f for a list of pids at arrays of points;
+``alphasQ2`` / ``alphasQ`` / ``py_alphasQ`` evaluate alpha_s; ``trace`` warms
+the kernels up and tunes the launch shape (HIP code is compiled ahead of time,
+so there is nothing to trace).
+
+torch provides device memory and the current stream; the computation itself
+is done by libpdfx's HIP kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+_PREC = {"f64": B.PDFX_F64, "fp64": B.PDFX_F64, "f32s": B.PDFX_F32S, "fp32": B.PDFX_F32S,
+         "f32": B.PDFX_F32S}
+_DOMAIN = {"nan": B.PDFX_DOMAIN_NAN, "clamp": B.PDFX_DOMAIN_CLAMP}
+
+
+def prec_code(prec) -> int:
+    return prec if isinstance(prec, int) else _PREC[prec]
+
+
+def prec_dtype(prec) -> torch.dtype:
+    return torch.float64 if prec_code(prec) == B.PDFX_F64 else torch.float32
+
+
+def _device_f64(a, device=None) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        if a.device.type != "cuda":
+            a = a.to(device or "cuda")
+        if a.dtype != torch.float64:
+            a = a.to(torch.float64)
+        return a.contiguous()
+    return torch.as_tensor(np.asarray(a, dtype=np.float64), device=device or "cuda")
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class PDF:
+    """One PDF member resident on the current GPU."""
+
+    def __init__(self, spec, with_values: bool = True):
+        self._desc = B.HostDesc.from_spec(spec, with_values)
+        self.handle = B.pdfx_load_grid(self._desc)
+        self.pids = np.array(spec.pids, dtype=np.int32)
+        self.n_flav, self.n_x, self.n_q, self.n_sub, self.n_as = B.pdfx_grid_shape(self.handle)
+        self.shape = (self.n_flav, self.n_x, self.n_q)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.pdfx_free_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- PDF --
+    def xfxQ2(self, pids, x, q2, prec="f64", values=None, domain="nan", out=None):
+        """x f for each pid (columns, request order) at each point -> [n, len(pids)]."""
+        x = _device_f64(x)
+        q2 = _device_f64(q2, x.device)
+        pids = np.atleast_1d(np.asarray(pids, dtype=np.int32))
+        n = x.numel()
+        if out is None:
+            out = torch.empty((n, pids.shape[0]), dtype=prec_dtype(prec), device=x.device)
+        B.pdfx_eval_xfx(self.handle, _ptr(values), prec_code(prec), pids, x.data_ptr(),
+                        q2.data_ptr(), n, out.data_ptr(), _DOMAIN[domain], _stream(x.device))
+        return out
+
+    def xfxQ(self, pids, x, q, prec="f64", values=None, domain="nan", out=None):
+        x = _device_f64(x)
+        q = _device_f64(q, x.device)
+        pids = np.atleast_1d(np.asarray(pids, dtype=np.int32))
+        n = x.numel()
+        if out is None:
+            out = torch.empty((n, pids.shape[0]), dtype=prec_dtype(prec), device=x.device)
+        B.pdfx_eval_xfxQ(self.handle, _ptr(values), prec_code(prec), pids, x.data_ptr(),
+                         q.data_ptr(), n, out.data_ptr(), _DOMAIN[domain], _stream(x.device))
+        return out
+
+    py_xfxQ = xfxQ
+    py_xfxQ2 = xfxQ2
+
+    # -- alpha_s --
+    def alphasQ2(self, q2, prec="f64", domain="nan", out=None):
+        q2 = _device_f64(q2)
+        n = q2.numel()
+        if out is None:
+            out = torch.empty(n, dtype=prec_dtype(prec), device=q2.device)
+        B.pdfx_eval_alphas(self.handle, q2.data_ptr(), n, out.data_ptr(), prec_code(prec),
+                           _DOMAIN[domain], _stream(q2.device))
+        return out
+
+    def alphasQ(self, q, prec="f64", domain="nan", out=None):
+        q = _device_f64(q)
+        return self.alphasQ2(q * q, prec, domain, out)
+
+    py_alphasQ = alphasQ
+
+    # -- misc --
+    def domain_errors(self) -> int:
+        return B.pdfx_domain_errors(self.handle)
+
+    def launch(self, prec="f64"):
+        return B.pdfx_get_launch(self.handle, prec_code(prec))
+
+    def set_launch(self, prec, block, ppt):
+        B.pdfx_set_launch(self.handle, prec_code(prec), block, ppt)
+
+    def autotune(self, prec="f64", n_req=None, n_pts=1 << 22, cache_path=None):
+        B.pdfx_autotune(self.handle, prec_code(prec), n_req or self.n_flav, n_pts, cache_path)
+        return self.launch(prec)
+
+    def trace(self, n_pts=1 << 20, tune=True):
+        """Warm-up: one small call per precision (and a launch-shape tune)."""
+        for prec in ("f64", "f32s"):
+            if tune:
+                try:
+                    self.autotune(prec, n_pts=n_pts)
+                except B.PdfxError:
+                    pass
+            x = torch.full((256,), 0.1, dtype=torch.float64, device="cuda")
+            self.xfxQ2(self.pids, x, torch.full_like(x, 100.0), prec=prec)
+        torch.cuda.synchronize()
+
+    alphas_trace = trace
+
+
+def mkPDF(spec, with_values: bool = True) -> PDF:
+    """Build a PDF object for one member (the paper's mkPDF, Sec. 2.1)."""
+    return PDF(spec, with_values)

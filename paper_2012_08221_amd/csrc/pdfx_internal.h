@@ -1,0 +1,85 @@
+// Internal types shared by the pdfx host runtime and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdfx {
+
+// Per-interval record of one interpolation axis (x, or the concatenated Q^2
+// subgrids, or the alpha_s knots).  For the interval [z_i, z_{i+1}] in ln
+// space, with t = (ln v - z_i) * inv_d and the cubic Hermite basis h.., the
+// four knot weights of knots (i-1, i, i+1, i+2) are
+//   w_-1 = -h10 pl
+//   w_0  =  h00 + h10 (pl - ql) - h11 qr
+//   w_1  =  h01 + h10 ql + h11 (qr - pr)
+//   w_2  =  h11 pr
+// where, for the finite-difference slopes of the method (one-sided at an end
+// of the axis or subgrid, mean of the neighbouring divided differences
+// inside), cl = 1/2 inside and 0 at the left end, cr likewise at the right end,
+// pl = cl * d_i / d_{i-1}, ql = 1 - cl, pr = cr * d_i / d_{i+1}, qr = 1 - cr.
+// A weight on a knot outside the axis/subgrid is exactly 0.
+template <typename T>
+struct alignas(8 * sizeof(T)) IntervalRec {
+    T z;      // ln z_i   (FP64 in both tables: t is formed in FP64)
+    T inv_d;  // 1 / (ln z_{i+1} - ln z_i)
+    T pl, plql, ql, qr, qrpr, pr;  // pl, pl-ql, ql, qr, qr-pr, pr
+};
+
+// Device view of one axis.
+struct AxisDev {
+    const double *knots;          // raw knots, non-decreasing (search on raw values)
+    const IntervalRec<double> *rec64;
+    const IntervalRec<float> *rec32;  // z and inv_d unused (kept FP64 in rec64)
+    const uint16_t *seed;         // bucket -> starting interval for the search
+    int n;                        // knots
+    int nbuckets;
+    double lo;                    // raw knots[0]
+    double hi;                    // raw knots[n-1]
+    double ln_lo;                 // ln knots[0]
+    double inv_hb;                // nbuckets / (ln knots[n-1] - ln knots[0])
+};
+
+constexpr int kMaxReq = 64;
+
+struct XfxArgs {
+    AxisDev ax, aq;
+    const void *vals;             // [nf][nx][nq] FP64 or FP32
+    int nf, nx, nq;
+    int n_req;
+    int rows[kMaxReq];            // grid row per output column, -1 = absent pid
+    const double *x;
+    const double *q;              // Q^2, or Q if q_is_q
+    int q_is_q;
+    void *out;
+    int64_t n;
+    int domain_mode;
+    unsigned long long *dom_count;
+};
+
+struct AlphasArgs {
+    AxisDev a;
+    const void *vals;             // padded [n+2] FP64 or FP32: vals[k+1] = alpha_s knot k
+    const double *q2;
+    void *out;
+    int64_t n;
+    int domain_mode;
+    unsigned long long *dom_count;
+};
+
+// Launch shapes compiled for the forward kernels.
+struct LaunchShape {
+    int block;
+    int ppt;
+};
+
+// Kernel launchers (xfx_fwd.hip).  Return a hipError_t.
+hipError_t launch_xfx_f64(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
+hipError_t launch_xfx_f32s(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
+hipError_t launch_alphas(const AlphasArgs &a, bool f32, hipStream_t s);
+bool launch_shape_supported(LaunchShape ls);
+int n_launch_shapes();
+LaunchShape launch_shape_at(int i);
+size_t xfx_lds_bytes(int nx, int nq, bool f32);
+
+}  // namespace pdfx

@@ -1,0 +1,556 @@
+// Host runtime behind the pdfx C-ABI: descriptor validation, FP64 derivation
+// of the per-interval tables, device upload, launch-shape selection and the
+// eval entry points.  Kernels live in the other .hip files of this directory.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pdfx.h"
+#include "pdfx_internal.h"
+#include "runtime_internal.h"
+
+using namespace pdfx;
+
+namespace pdfx {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? PDFX_ENOMEM : PDFX_EHIP, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+DeviceBuf::~DeviceBuf()
+{
+    if (ptr)
+        (void)hipFree(ptr);
+}
+
+hipError_t DeviceBuf::upload(const void *src, size_t n)
+{
+    if (ptr) {
+        (void)hipFree(ptr);
+        ptr = nullptr;
+    }
+    bytes = n;
+    if (n == 0)
+        return hipSuccess;
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return e;
+    }
+    if (src)
+        e = hipMemcpy(ptr, src, n, hipMemcpyHostToDevice);
+    else
+        e = hipMemset(ptr, 0, n);
+    return e;
+}
+
+static int canonical_pid(int p) { return p == 0 ? 21 : p; }
+
+// Checks a knot axis made of subgrids [off[s], off[s+1]): raw knots finite and
+// > 0, strictly increasing inside a subgrid, neighbouring subgrids sharing the
+// boundary knot value.
+static int check_axis(const double *z, const int32_t *off, int n_sub, const char *name)
+{
+    for (int s = 0; s < n_sub; ++s) {
+        if (off[s + 1] - off[s] < 2)
+            return fail(PDFX_EINVAL, "%s: subgrid %d has fewer than 2 knots", name, s);
+        for (int k = off[s]; k < off[s + 1]; ++k) {
+            if (!std::isfinite(z[k]) || !(z[k] > 0.0))
+                return fail(PDFX_EINVAL, "%s: knot %d is not finite and positive", name, k);
+            if (k > off[s] && !(z[k] > z[k - 1]))
+                return fail(PDFX_EINVAL, "%s: knots not strictly increasing at %d", name, k);
+        }
+        if (s + 1 < n_sub && z[off[s + 1] - 1] != z[off[s + 1]])
+            return fail(PDFX_EINVAL, "%s: boundary knot of subgrids %d/%d not repeated", name, s,
+                        s + 1);
+    }
+    return PDFX_OK;
+}
+
+// Builds the host tables of one axis (see IntervalRec) and uploads them.
+int AxisHost::build(const double *z, const int32_t *off, int n_sub)
+{
+    n = off[n_sub];
+    knots.assign(z, z + n);
+    std::vector<double> ln(n);
+    for (int k = 0; k < n; ++k)
+        ln[k] = std::log(z[k]);
+    rec64.assign(n > 1 ? n - 1 : 1, IntervalRec<double>{});
+    rec32.assign(n > 1 ? n - 1 : 1, IntervalRec<float>{});
+    for (int s = 0; s < n_sub; ++s) {
+        const int a = off[s], b = off[s + 1];  // knots a..b-1
+        for (int i = a; i + 1 < b; ++i) {
+            const double d = ln[i + 1] - ln[i];
+            const bool left = i > a, right = i + 1 < b - 1;
+            const double cl = left ? 0.5 : 0.0, cr = right ? 0.5 : 0.0;
+            const double rm = left ? d / (ln[i] - ln[i - 1]) : 0.0;
+            const double rp = right ? d / (ln[i + 2] - ln[i + 1]) : 0.0;
+            IntervalRec<double> r;
+            r.z = ln[i];
+            r.inv_d = 1.0 / d;
+            r.pl = cl * rm;
+            r.ql = 1.0 - cl;
+            r.plql = r.pl - r.ql;
+            r.pr = cr * rp;
+            r.qr = 1.0 - cr;
+            r.qrpr = r.qr - r.pr;
+            rec64[i] = r;
+            IntervalRec<float> f;
+            f.z = 0.f;
+            f.inv_d = 0.f;
+            f.pl = (float)r.pl;
+            f.plql = (float)r.plql;
+            f.ql = (float)r.ql;
+            f.qr = (float)r.qr;
+            f.qrpr = (float)r.qrpr;
+            f.pr = (float)r.pr;
+            rec32[i] = f;
+        }
+    }
+    // Bucket seeds over [ln z_0, ln z_{n-1}]: seed[b] = largest interval whose
+    // start is <= the bucket's lower edge (clamped to n-2).
+    nbuckets = std::min(4096, std::max(64, 4 * n));
+    ln_lo = ln[0];
+    const double span = ln[n - 1] - ln[0];
+    inv_hb = nbuckets / span;
+    seed.assign(nbuckets, 0);
+    int i = 0;
+    for (int b = 0; b < nbuckets; ++b) {
+        const double edge = ln_lo + b * (span / nbuckets);
+        while (i + 1 < n - 1 && ln[i + 1] <= edge)
+            ++i;
+        seed[b] = (uint16_t)i;
+    }
+    hipError_t e;
+    if ((e = d_knots.upload(knots.data(), sizeof(double) * n)) != hipSuccess)
+        return fail_hip(e, "upload knots");
+    if ((e = d_rec64.upload(rec64.data(), sizeof(rec64[0]) * rec64.size())) != hipSuccess)
+        return fail_hip(e, "upload interval table");
+    if ((e = d_rec32.upload(rec32.data(), sizeof(rec32[0]) * rec32.size())) != hipSuccess)
+        return fail_hip(e, "upload interval table");
+    if ((e = d_seed.upload(seed.data(), sizeof(uint16_t) * nbuckets)) != hipSuccess)
+        return fail_hip(e, "upload seeds");
+    return PDFX_OK;
+}
+
+AxisDev AxisHost::dev() const
+{
+    AxisDev a;
+    a.knots = (const double *)d_knots.ptr;
+    a.rec64 = (const IntervalRec<double> *)d_rec64.ptr;
+    a.rec32 = (const IntervalRec<float> *)d_rec32.ptr;
+    a.seed = (const uint16_t *)d_seed.ptr;
+    a.n = n;
+    a.nbuckets = nbuckets;
+    a.lo = knots.front();
+    a.hi = knots.back();
+    a.ln_lo = ln_lo;
+    a.inv_hb = inv_hb;
+    return a;
+}
+
+int device_cu_count()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
+}
+
+size_t device_max_lds()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 64 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+        return 64 * 1024;
+    return (size_t)v;
+}
+
+int validate_desc(const pdfx_grid_desc *d, bool need_values)
+{
+    if (!d)
+        return fail(PDFX_EINVAL, "descriptor is NULL");
+    if (d->n_flav < 1 || d->n_flav > kMaxReq)
+        return fail(PDFX_EINVAL, "n_flav = %d outside [1, %d]", d->n_flav, kMaxReq);
+    if (!d->pids)
+        return fail(PDFX_EINVAL, "pids is NULL");
+    for (int f = 0; f < d->n_flav; ++f)
+        for (int g = 0; g < f; ++g)
+            if (canonical_pid(d->pids[f]) == canonical_pid(d->pids[g]))
+                return fail(PDFX_EINVAL, "pid %d appears twice", d->pids[f]);
+    if (d->n_x < 2 || d->n_x > 4096)
+        return fail(PDFX_EINVAL, "n_x = %d outside [2, 4096]", d->n_x);
+    if (!d->x)
+        return fail(PDFX_EINVAL, "x knots are NULL");
+    if (d->n_sub < 1 || d->n_sub > 16)
+        return fail(PDFX_EINVAL, "n_sub = %d outside [1, 16]", d->n_sub);
+    if (!d->q_off || !d->q2)
+        return fail(PDFX_EINVAL, "q_off or q2 is NULL");
+    if (d->q_off[0] != 0)
+        return fail(PDFX_EINVAL, "q_off[0] must be 0");
+    for (int s = 0; s < d->n_sub; ++s)
+        if (d->q_off[s + 1] <= d->q_off[s])
+            return fail(PDFX_EINVAL, "q_off not increasing at %d", s);
+    if (d->q_off[d->n_sub] > 4096)
+        return fail(PDFX_EINVAL, "n_q = %d above 4096", d->q_off[d->n_sub]);
+    const int32_t xoff[2] = {0, d->n_x};
+    int rc;
+    if ((rc = check_axis(d->x, xoff, 1, "x")) != PDFX_OK)
+        return rc;
+    if ((rc = check_axis(d->q2, d->q_off, d->n_sub, "q2")) != PDFX_OK)
+        return rc;
+    if (xfx_lds_bytes(d->n_x, d->q_off[d->n_sub], true) > device_lds_limit())
+        return fail(PDFX_EINVAL, "grid %dx%d too large for one LDS slab", d->n_x,
+                    d->q_off[d->n_sub]);
+    if (need_values && !d->xf)
+        return fail(PDFX_EINVAL, "values (xf) are required here");
+    if (d->xf) {
+        const size_t nv = (size_t)d->n_flav * d->n_x * d->q_off[d->n_sub];
+        for (size_t i = 0; i < nv; ++i)
+            if (!std::isfinite(d->xf[i]))
+                return fail(PDFX_EINVAL, "value %zu is not finite", i);
+    }
+    if (d->n_as < 0)
+        return fail(PDFX_EINVAL, "n_as < 0");
+    if (d->n_as > 0) {
+        if (!d->as_q2 || !d->as_val)
+            return fail(PDFX_EINVAL, "alpha_s arrays are NULL");
+        std::vector<int32_t> off{0};
+        for (int j = 0; j + 1 < d->n_as; ++j)
+            if (d->as_q2[j] == d->as_q2[j + 1])
+                off.push_back(j + 1);
+        off.push_back(d->n_as);
+        if ((rc = check_axis(d->as_q2, off.data(), (int)off.size() - 1, "alpha_s q2")) != PDFX_OK)
+            return rc;
+        for (int j = 0; j < d->n_as; ++j)
+            if (!std::isfinite(d->as_val[j]))
+                return fail(PDFX_EINVAL, "alpha_s value %d is not finite", j);
+    }
+    return PDFX_OK;
+}
+
+size_t device_lds_limit() { return 160 * 1024; }
+
+}  // namespace pdfx
+
+int pdfx_grid::row_of(int pid) const
+{
+    const int p = pdfx::canonical_pid(pid);
+    for (int f = 0; f < nf; ++f)
+        if (pdfx::canonical_pid(pids[f]) == p)
+            return f;
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *pdfx_last_error(void) { return pdfx::g_last_error.c_str(); }
+
+const char *pdfx_version(void) { return "pdfx 0.1 (gfx950)"; }
+
+int pdfx_load_grid(const pdfx_grid_desc *d, pdfx_grid **out)
+{
+    clear_error();
+    if (!out)
+        return fail(PDFX_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_desc(d, false);
+    if (rc != PDFX_OK)
+        return rc;
+    pdfx_grid *g = new pdfx_grid();
+    rc = grid_init(g, d);
+    if (rc != PDFX_OK) {
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return PDFX_OK;
+}
+
+void pdfx_free_grid(pdfx_grid *g) { delete g; }
+
+int pdfx_grid_shape(const pdfx_grid *g, int32_t *n_flav, int32_t *n_x, int32_t *n_q,
+                    int32_t *n_sub, int32_t *n_as)
+{
+    clear_error();
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (n_flav)
+        *n_flav = g->nf;
+    if (n_x)
+        *n_x = g->ax.n;
+    if (n_q)
+        *n_q = g->aq.n;
+    if (n_sub)
+        *n_sub = g->n_sub;
+    if (n_as)
+        *n_as = g->has_alphas ? g->aa.n : 0;
+    return PDFX_OK;
+}
+
+static int eval_xfx_common(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
+                           int32_t n_req, const double *x, const double *q, int64_t n_pts,
+                           void *out, int domain_mode, void *stream, int q_is_q)
+{
+    clear_error();
+    XfxArgs a;
+    int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q, n_pts, out, domain_mode, &a);
+    if (rc != PDFX_OK || n_pts == 0)
+        return rc;
+    a.q_is_q = q_is_q;
+    return run_xfx(g, a, prec, (hipStream_t)stream);
+}
+
+int pdfx_eval_xfx(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
+                  int32_t n_req, const double *x, const double *q2, int64_t n_pts, void *out,
+                  int domain_mode, void *stream)
+{
+    return eval_xfx_common(g, xf_dev, prec, pids, n_req, x, q2, n_pts, out, domain_mode, stream,
+                           0);
+}
+
+int pdfx_eval_xfxQ(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
+                   int32_t n_req, const double *x, const double *q, int64_t n_pts, void *out,
+                   int domain_mode, void *stream)
+{
+    return eval_xfx_common(g, xf_dev, prec, pids, n_req, x, q, n_pts, out, domain_mode, stream, 1);
+}
+
+int pdfx_eval_alphas(const pdfx_grid *g, const double *q2, int64_t n, void *out, int prec,
+                     int domain_mode, void *stream)
+{
+    clear_error();
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (!g->has_alphas)
+        return fail(PDFX_ENOALPHAS, "grid has no alpha_s knots");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP)
+        return fail(PDFX_EINVAL, "unknown domain mode %d", domain_mode);
+    if (n < 0)
+        return fail(PDFX_EINVAL, "n < 0");
+    if (n == 0)
+        return PDFX_OK;
+    if (!q2 || !out)
+        return fail(PDFX_EINVAL, "q2 or out is NULL");
+    AlphasArgs a;
+    a.a = g->aa.dev();
+    a.vals = prec == PDFX_F64 ? g->as_vals64.ptr : g->as_vals32.ptr;
+    a.q2 = q2;
+    a.out = out;
+    a.n = n;
+    a.domain_mode = domain_mode;
+    a.dom_count = (unsigned long long *)g->dom_count.ptr;
+    hipError_t e = launch_alphas(a, prec == PDFX_F32S, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "alpha_s launch");
+    return PDFX_OK;
+}
+
+int pdfx_domain_errors(const pdfx_grid *g, int64_t *count)
+{
+    clear_error();
+    if (!g || !count)
+        return fail(PDFX_EINVAL, "grid or count is NULL");
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return fail_hip(e, "synchronize");
+    unsigned long long v = 0;
+    e = hipMemcpy(&v, g->dom_count.ptr, sizeof v, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return fail_hip(e, "read domain counter");
+    e = hipMemset(g->dom_count.ptr, 0, sizeof v);
+    if (e != hipSuccess)
+        return fail_hip(e, "reset domain counter");
+    *count = (int64_t)v;
+    return PDFX_OK;
+}
+
+int pdfx_get_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt)
+{
+    clear_error();
+    if (!g || !block || !ppt)
+        return fail(PDFX_EINVAL, "NULL argument");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    *block = g->shape[prec].block;
+    *ppt = g->shape[prec].ppt;
+    return PDFX_OK;
+}
+
+int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
+{
+    clear_error();
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    LaunchShape ls{block, ppt};
+    if (!launch_shape_supported(ls))
+        return fail(PDFX_EINVAL, "launch shape (%d, %d) not compiled", block, ppt);
+    g->shape[prec] = ls;
+    return PDFX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// grid construction and the forward launch
+// ---------------------------------------------------------------------------
+
+namespace pdfx {
+
+int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
+{
+    g->nf = d->n_flav;
+    g->n_sub = d->n_sub;
+    g->pids.assign(d->pids, d->pids + d->n_flav);
+    g->q_off.assign(d->q_off, d->q_off + d->n_sub + 1);
+    const int32_t xoff[2] = {0, d->n_x};
+    int rc;
+    if ((rc = g->ax.build(d->x, xoff, 1)) != PDFX_OK)
+        return rc;
+    if ((rc = g->aq.build(d->q2, d->q_off, d->n_sub)) != PDFX_OK)
+        return rc;
+    hipError_t e;
+    if (d->xf) {
+        const size_t nv = (size_t)d->n_flav * d->n_x * g->aq.n;
+        std::vector<float> v32(nv);
+        for (size_t i = 0; i < nv; ++i)
+            v32[i] = (float)d->xf[i];
+        if ((e = g->vals64.upload(d->xf, nv * sizeof(double))) != hipSuccess)
+            return fail_hip(e, "upload values");
+        if ((e = g->vals32.upload(v32.data(), nv * sizeof(float))) != hipSuccess)
+            return fail_hip(e, "upload values");
+        g->has_values = true;
+    }
+    if (d->n_as > 0) {
+        std::vector<int32_t> off{0};
+        for (int j = 0; j + 1 < d->n_as; ++j)
+            if (d->as_q2[j] == d->as_q2[j + 1])
+                off.push_back(j + 1);
+        off.push_back(d->n_as);
+        if ((rc = g->aa.build(d->as_q2, off.data(), (int)off.size() - 1)) != PDFX_OK)
+            return rc;
+        std::vector<double> p64(d->n_as + 2, 0.0);
+        std::vector<float> p32(d->n_as + 2, 0.f);
+        for (int j = 0; j < d->n_as; ++j) {
+            p64[j + 1] = d->as_val[j];
+            p32[j + 1] = (float)d->as_val[j];
+        }
+        if ((e = g->as_vals64.upload(p64.data(), p64.size() * sizeof(double))) != hipSuccess)
+            return fail_hip(e, "upload alpha_s");
+        if ((e = g->as_vals32.upload(p32.data(), p32.size() * sizeof(float))) != hipSuccess)
+            return fail_hip(e, "upload alpha_s");
+        g->has_alphas = true;
+    }
+    if ((e = g->dom_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess)
+        return fail_hip(e, "allocate domain counter");
+    g->shape[PDFX_F64] = default_shape(false);
+    g->shape[PDFX_F32S] = default_shape(true);
+    g->cus = device_cu_count();
+    return PDFX_OK;
+}
+
+LaunchShape default_shape(bool f32) { return f32 ? LaunchShape{256, 4} : LaunchShape{256, 4}; }
+
+int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
+                     int32_t n_req, const double *x, const double *q, int64_t n_pts, void *out,
+                     int domain_mode, XfxArgs *a)
+{
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP)
+        return fail(PDFX_EINVAL, "unknown domain mode %d", domain_mode);
+    if (n_req < 1 || n_req > PDFX_MAX_REQ)
+        return fail(PDFX_EINVAL, "n_req = %d outside [1, %d]", n_req, PDFX_MAX_REQ);
+    if (!pids)
+        return fail(PDFX_EINVAL, "pids is NULL");
+    if (n_pts < 0)
+        return fail(PDFX_EINVAL, "n_pts < 0");
+    if (prec == PDFX_F64 && xfx_lds_bytes(g->ax.n, g->aq.n, false) > device_lds_limit())
+        return fail(PDFX_EINVAL, "grid too large for an FP64 LDS slab; use PDFX_F32S");
+    const void *vals = xf_dev ? xf_dev : (prec == PDFX_F64 ? g->vals64.ptr : g->vals32.ptr);
+    if (!vals)
+        return fail(PDFX_ENOVALUES, "grid has no owned values and xf_dev is NULL");
+    if (n_pts > 0 && (!x || !q || !out))
+        return fail(PDFX_EINVAL, "x, q2 or out is NULL");
+    const uintptr_t mask = (uintptr_t)7;
+    if (((uintptr_t)x & mask) || ((uintptr_t)q & mask) || ((uintptr_t)vals & 3) ||
+        ((uintptr_t)out & 3))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    a->ax = g->ax.dev();
+    a->aq = g->aq.dev();
+    a->vals = vals;
+    a->nf = g->nf;
+    a->nx = g->ax.n;
+    a->nq = g->aq.n;
+    a->n_req = n_req;
+    for (int r = 0; r < kMaxReq; ++r)
+        a->rows[r] = -1;
+    for (int r = 0; r < n_req; ++r)
+        a->rows[r] = g->row_of(pids[r]);
+    a->x = x;
+    a->q = q;
+    a->q_is_q = 0;
+    a->out = out;
+    a->n = n_pts;
+    a->domain_mode = domain_mode;
+    a->dom_count = (unsigned long long *)g->dom_count.ptr;
+    return PDFX_OK;
+}
+
+int max_resident_blocks(LaunchShape ls, size_t lds, int cus)
+{
+    int by_lds = (int)(device_lds_limit() / (lds > 0 ? lds : 1));
+    int by_threads = 2048 / ls.block;
+    int per_cu = by_lds < by_threads ? by_lds : by_threads;
+    if (per_cu < 1)
+        per_cu = 1;
+    return per_cu * cus;
+}
+
+int run_xfx(const pdfx_grid *g, const XfxArgs &a, int prec, hipStream_t s)
+{
+    const LaunchShape ls = g->shape[prec];
+    const bool f32 = prec == PDFX_F32S;
+    const int maxb = max_resident_blocks(ls, xfx_lds_bytes(a.nx, a.nq, f32), g->cus);
+    hipError_t e = f32 ? launch_xfx_f32s(a, ls, maxb, s) : launch_xfx_f64(a, ls, maxb, s);
+    if (e != hipSuccess)
+        return fail_hip(e, "xfx launch");
+    return PDFX_OK;
+}
+
+}  // namespace pdfx

@@ -1,0 +1,76 @@
+// Host-side objects of the pdfx runtime (not part of the C-ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pdfx.h"
+#include "pdfx_internal.h"
+
+namespace pdfx {
+
+// Owning device allocation.
+struct DeviceBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DeviceBuf() = default;
+    DeviceBuf(const DeviceBuf &) = delete;
+    DeviceBuf &operator=(const DeviceBuf &) = delete;
+    ~DeviceBuf();
+    // Allocates n bytes and copies src (or zero-fills if src is NULL).
+    hipError_t upload(const void *src, size_t n);
+};
+
+// One interpolation axis: host tables derived in FP64, plus their device copies.
+struct AxisHost {
+    int n = 0;
+    int nbuckets = 0;
+    double ln_lo = 0.0;
+    double inv_hb = 0.0;
+    std::vector<double> knots;
+    std::vector<IntervalRec<double>> rec64;
+    std::vector<IntervalRec<float>> rec32;
+    std::vector<uint16_t> seed;
+    DeviceBuf d_knots, d_rec64, d_rec32, d_seed;
+    int build(const double *z, const int32_t *off, int n_sub);
+    AxisDev dev() const;
+};
+
+int fail(int code, const char *fmt, ...);
+int fail_hip(hipError_t e, const char *what);
+void clear_error();
+int validate_desc(const pdfx_grid_desc *d, bool need_values);
+size_t device_lds_limit();
+int device_cu_count();
+LaunchShape default_shape(bool f32);
+int max_resident_blocks(LaunchShape ls, size_t lds, int cus);
+
+}  // namespace pdfx
+
+struct pdfx_grid {
+    int nf = 0;
+    int n_sub = 0;
+    int cus = 256;
+    bool has_values = false;
+    bool has_alphas = false;
+    std::vector<int32_t> pids;
+    std::vector<int32_t> q_off;
+    pdfx::AxisHost ax, aq, aa;
+    pdfx::DeviceBuf vals64, vals32;         // [nf][nx][nq]
+    pdfx::DeviceBuf as_vals64, as_vals32;   // padded [n_as + 2]
+    pdfx::DeviceBuf dom_count;              // unsigned long long
+    pdfx::LaunchShape shape[2];             // per precision
+    int row_of(int pid) const;
+};
+
+namespace pdfx {
+
+int grid_init(pdfx_grid *g, const pdfx_grid_desc *d);
+int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
+                     int32_t n_req, const double *x, const double *q, int64_t n_pts, void *out,
+                     int domain_mode, XfxArgs *a);
+int run_xfx(const pdfx_grid *g, const XfxArgs &a, int prec, hipStream_t s);
+
+}  // namespace pdfx
