@@ -26,6 +26,11 @@ PDFX_DOMAIN_NAN = 0
 PDFX_DOMAIN_CLAMP = 1
 PDFX_MAX_REQ = 64
 
+# Launch shapes (workgroup size, points per thread) compiled into the forward
+# kernels; a negative count selects the store-as-you-go variant.
+LAUNCH_SHAPES = ((256, 2), (256, 4), (512, 1), (512, 2), (1024, 1),
+                 (256, -2), (256, -4), (256, -8), (512, -2), (512, -4), (1024, -1), (1024, -2))
+
 # Every function the header declares, in header order.
 EXPORTS = (
     "pdfx_load_grid", "pdfx_free_grid", "pdfx_grid_shape", "pdfx_eval_xfx", "pdfx_eval_xfxQ",
@@ -59,6 +64,13 @@ def lib():
     """The loaded library; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname as ROCm's;
+        # load torch first so that one runtime serves both (a second runtime
+        # loaded under torch hides the GPUs from it).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libpdfx.so is not built (run __graft_entry__.build() or "
                                "python paper_2012_08221_amd/build.py); no fallback exists")

@@ -21,19 +21,19 @@ namespace pdfx {
 // A weight on a knot outside the axis/subgrid is exactly 0.
 template <typename T>
 struct alignas(8 * sizeof(T)) IntervalRec {
-    T z;      // ln z_i   (FP64 in both tables: t is formed in FP64)
+    T z;      // ln z_i   (only the FP64 table's z and inv_d are used: t is formed in FP64)
     T inv_d;  // 1 / (ln z_{i+1} - ln z_i)
     T pl, plql, ql, qr, qrpr, pr;  // pl, pl-ql, ql, qr, qr-pr, pr
 };
 
-// Device view of one axis.
+// Device view of one axis (global-memory tables).
 struct AxisDev {
     const double *knots;          // raw knots, non-decreasing (search on raw values)
     const IntervalRec<double> *rec64;
-    const IntervalRec<float> *rec32;  // z and inv_d unused (kept FP64 in rec64)
+    const IntervalRec<float> *rec32;
     const uint16_t *seed;         // bucket -> starting interval for the search
     int n;                        // knots
-    int nbuckets;
+    int nbuckets;                 // multiple of 4
     double lo;                    // raw knots[0]
     double hi;                    // raw knots[n-1]
     double ln_lo;                 // ln knots[0]
@@ -42,19 +42,35 @@ struct AxisDev {
 
 constexpr int kMaxReq = 64;
 
+// Byte offsets of one axis' tables inside the workgroup's LDS.
+struct AxisLds {
+    int knots, seed, rec64, rec32;
+};
+
 struct XfxArgs {
     AxisDev ax, aq;
-    const void *vals;             // [nf][nx][nq] FP64 or FP32
+    // Values: one bordered slab per grid row, (nx+2) x (nq+2) with a zero
+    // border one knot wide, row-major (Q fastest), slab stride slab_elems
+    // elements (a multiple of 16 bytes).
+    const void *vals;
     int nf, nx, nq;
-    int n_req;
-    int rows[kMaxReq];            // grid row per output column, -1 = absent pid
+    int slab_elems;
+    int n_req;                    // output columns
+    int n_u;                      // distinct grid rows among the requested pids
+    int urow[kMaxReq];            // grid row of distinct u
+    int ucol_off[kMaxReq + 1];    // its output columns: ucols[ucol_off[u] .. ucol_off[u+1])
+    int ucols[kMaxReq];
+    int n_zero;                   // columns of pids absent from the grid (always 0)
+    int zcols[kMaxReq];
     const double *x;
     const double *q;              // Q^2, or Q if q_is_q
     int q_is_q;
-    void *out;
+    void *out;                    // [n][n_req]
     int64_t n;
     int domain_mode;
     unsigned long long *dom_count;
+    AxisLds lx, lq;               // table offsets in LDS
+    int lds_slab0, lds_slab1;     // slab buffer offsets in LDS
 };
 
 struct AlphasArgs {
@@ -67,19 +83,36 @@ struct AlphasArgs {
     unsigned long long *dom_count;
 };
 
-// Launch shapes compiled for the forward kernels.
+struct RepackArgs {
+    const void *src;              // [nf][nx][nq]
+    void *dst;                    // [nf][slab_elems] bordered
+    int nf, nx, nq, slab_elems;
+};
+
+// Launch shape of the forward kernel.
 struct LaunchShape {
     int block;
     int ppt;
 };
 
-// Kernel launchers (xfx_fwd.hip).  Return a hipError_t.
+// Kernel launchers.  Return a hipError_t.
 hipError_t launch_xfx_f64(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
 hipError_t launch_xfx_f32s(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
+hipError_t xfx_occupancy_f64(const XfxArgs &a, LaunchShape ls, int *blocks_per_cu);
+hipError_t xfx_occupancy_f32s(const XfxArgs &a, LaunchShape ls, int *blocks_per_cu);
 hipError_t launch_alphas(const AlphasArgs &a, bool f32, hipStream_t s);
+hipError_t launch_repack(const RepackArgs &a, bool f32, hipStream_t s);
 bool launch_shape_supported(LaunchShape ls);
 int n_launch_shapes();
 LaunchShape launch_shape_at(int i);
-size_t xfx_lds_bytes(int nx, int nq, bool f32);
+
+// LDS layout of the forward kernel for a grid: fills the offsets in a and
+// returns the total bytes (0 if even one slab does not fit).  double_buffer
+// receives whether two slabs fit.
+size_t xfx_lds_layout(XfxArgs &a, bool f32, bool *double_buffer);
+// Elements per bordered slab, rounded up to 16 bytes.
+int slab_elems_for(int nx, int nq, bool f32);
+
+constexpr size_t kLdsLimit = 160 * 1024;
 
 }  // namespace pdfx

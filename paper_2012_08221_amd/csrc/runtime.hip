@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -180,17 +181,6 @@ int device_cu_count()
     return cus;
 }
 
-size_t device_max_lds()
-{
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess)
-        return 64 * 1024;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-        v <= 0)
-        return 64 * 1024;
-    return (size_t)v;
-}
-
 int validate_desc(const pdfx_grid_desc *d, bool need_values)
 {
     if (!d)
@@ -224,7 +214,7 @@ int validate_desc(const pdfx_grid_desc *d, bool need_values)
         return rc;
     if ((rc = check_axis(d->q2, d->q_off, d->n_sub, "q2")) != PDFX_OK)
         return rc;
-    if (xfx_lds_bytes(d->n_x, d->q_off[d->n_sub], true) > device_lds_limit())
+    if (!grid_fits_lds(d->n_x, d->q_off[d->n_sub], d->n_as, true))
         return fail(PDFX_EINVAL, "grid %dx%d too large for one LDS slab", d->n_x,
                     d->q_off[d->n_sub]);
     if (need_values && !d->xf)
@@ -254,7 +244,6 @@ int validate_desc(const pdfx_grid_desc *d, bool need_values)
     return PDFX_OK;
 }
 
-size_t device_lds_limit() { return 160 * 1024; }
 
 }  // namespace pdfx
 
@@ -327,7 +316,7 @@ static int eval_xfx_common(const pdfx_grid *g, const void *xf_dev, int prec, con
     if (rc != PDFX_OK || n_pts == 0)
         return rc;
     a.q_is_q = q_is_q;
-    return run_xfx(g, a, prec, (hipStream_t)stream);
+    return run_xfx(g, a, xf_dev, prec, (hipStream_t)stream);
 }
 
 int pdfx_eval_xfx(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
@@ -430,6 +419,72 @@ int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
 
 namespace pdfx {
 
+int slab_elems_for(int nx, int nq, bool f32)
+{
+    const int per16 = f32 ? 4 : 2;
+    const int e = (nx + 2) * (nq + 2);
+    return (e + per16 - 1) / per16 * per16;
+}
+
+// LDS layout of the forward kernel: x tables, Q^2 tables, then one or two slabs.
+size_t xfx_lds_layout(XfxArgs &a, bool f32, bool *double_buffer)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes, size_t align) {
+        off = (off + align - 1) / align * align;
+        const size_t r = off;
+        off += bytes;
+        return (int)r;
+    };
+    const AxisDev *axes[2] = {&a.ax, &a.aq};
+    AxisLds *lds[2] = {&a.lx, &a.lq};
+    for (int i = 0; i < 2; ++i) {
+        lds[i]->knots = take((size_t)axes[i]->n * 8, 16);
+        lds[i]->seed = take((size_t)axes[i]->nbuckets * 2, 16);
+        lds[i]->rec64 = take((size_t)(axes[i]->n - 1) * 64, 64);
+        lds[i]->rec32 = take(f32 ? (size_t)(axes[i]->n - 1) * 32 : 0, 64);
+    }
+    const size_t slab = (size_t)a.slab_elems * (f32 ? 4 : 8);
+    a.lds_slab0 = take(slab, 16);
+    if (off > kLdsLimit)
+        return 0;
+    if (off + slab <= kLdsLimit) {
+        a.lds_slab1 = take(slab, 16);
+        *double_buffer = true;
+    } else {
+        a.lds_slab1 = a.lds_slab0;
+        *double_buffer = false;
+    }
+    return off;
+}
+
+// A grid is usable if the tables plus one slab of the given precision fit LDS.
+bool grid_fits_lds(int nx, int nq, int n_as, bool f32)
+{
+    (void)n_as;
+    XfxArgs a{};
+    a.ax.n = nx;
+    a.ax.nbuckets = std::min(4096, std::max(64, 4 * nx));
+    a.aq.n = nq;
+    a.aq.nbuckets = std::min(4096, std::max(64, 4 * nq));
+    a.slab_elems = slab_elems_for(nx, nq, f32);
+    bool db = false;
+    return xfx_lds_layout(a, f32, &db) != 0;
+}
+
+template <typename V>
+static std::vector<V> bordered_slabs(const double *xf, int nf, int nx, int nq, int slab_elems)
+{
+    std::vector<V> out((size_t)nf * slab_elems, V(0));
+    const int nqp = nq + 2;
+    for (int f = 0; f < nf; ++f)
+        for (int i = 0; i < nx; ++i)
+            for (int k = 0; k < nq; ++k)
+                out[(size_t)f * slab_elems + (size_t)(i + 1) * nqp + (k + 1)] =
+                    (V)xf[((size_t)f * nx + i) * nq + k];
+    return out;
+}
+
 int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
 {
     g->nf = d->n_flav;
@@ -442,17 +497,24 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
         return rc;
     if ((rc = g->aq.build(d->q2, d->q_off, d->n_sub)) != PDFX_OK)
         return rc;
+    const int nx = g->ax.n, nq = g->aq.n;
+    g->slab_elems[PDFX_F64] = slab_elems_for(nx, nq, false);
+    g->slab_elems[PDFX_F32S] = slab_elems_for(nx, nq, true);
     hipError_t e;
     if (d->xf) {
-        const size_t nv = (size_t)d->n_flav * d->n_x * g->aq.n;
-        std::vector<float> v32(nv);
-        for (size_t i = 0; i < nv; ++i)
-            v32[i] = (float)d->xf[i];
-        if ((e = g->vals64.upload(d->xf, nv * sizeof(double))) != hipSuccess)
+        auto v64 = bordered_slabs<double>(d->xf, g->nf, nx, nq, g->slab_elems[PDFX_F64]);
+        auto v32 = bordered_slabs<float>(d->xf, g->nf, nx, nq, g->slab_elems[PDFX_F32S]);
+        if ((e = g->vals[PDFX_F64].upload(v64.data(), v64.size() * sizeof(double))) != hipSuccess)
             return fail_hip(e, "upload values");
-        if ((e = g->vals32.upload(v32.data(), nv * sizeof(float))) != hipSuccess)
+        if ((e = g->vals[PDFX_F32S].upload(v32.data(), v32.size() * sizeof(float))) != hipSuccess)
             return fail_hip(e, "upload values");
         g->has_values = true;
+    }
+    // bordered copies of caller-provided values land here
+    for (int p = 0; p < 2; ++p) {
+        const size_t bytes = (size_t)g->nf * g->slab_elems[p] * (p == PDFX_F64 ? 8 : 4);
+        if ((e = g->scratch_vals[p].upload(nullptr, bytes)) != hipSuccess)
+            return fail_hip(e, "allocate value scratch");
     }
     if (d->n_as > 0) {
         std::vector<int32_t> off{0};
@@ -462,8 +524,9 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
         off.push_back(d->n_as);
         if ((rc = g->aa.build(d->as_q2, off.data(), (int)off.size() - 1)) != PDFX_OK)
             return rc;
+        // padded: [0, a_0 .. a_{n-1}, 0], FP32 copy rounded up to an even length
         std::vector<double> p64(d->n_as + 2, 0.0);
-        std::vector<float> p32(d->n_as + 2, 0.f);
+        std::vector<float> p32((d->n_as + 3) / 2 * 2, 0.f);
         for (int j = 0; j < d->n_as; ++j) {
             p64[j + 1] = d->as_val[j];
             p32[j + 1] = (float)d->as_val[j];
@@ -482,7 +545,37 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
     return PDFX_OK;
 }
 
-LaunchShape default_shape(bool f32) { return f32 ? LaunchShape{256, 4} : LaunchShape{256, 4}; }
+LaunchShape default_shape(bool f32) { return f32 ? LaunchShape{512, 1} : LaunchShape{512, 1}; }
+
+// Request columns -> distinct grid rows (each staged once per tile) plus the
+// columns of absent pids.
+static void plan_columns(const pdfx_grid *g, const int32_t *pids, int n_req, XfxArgs *a)
+{
+    int rows[kMaxReq];
+    for (int r = 0; r < n_req; ++r)
+        rows[r] = g->row_of(pids[r]);
+    a->n_u = 0;
+    a->n_zero = 0;
+    int ncols = 0;
+    a->ucol_off[0] = 0;
+    bool used[kMaxReq] = {false};
+    for (int r = 0; r < n_req; ++r) {
+        if (rows[r] < 0) {
+            a->zcols[a->n_zero++] = r;
+            continue;
+        }
+        if (used[r])
+            continue;
+        const int u = a->n_u++;
+        a->urow[u] = rows[r];
+        for (int c = r; c < n_req; ++c)
+            if (rows[c] == rows[r]) {
+                a->ucols[ncols++] = c;
+                used[c] = true;
+            }
+        a->ucol_off[u + 1] = ncols;
+    }
+}
 
 int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
                      int32_t n_req, const double *x, const double *q, int64_t n_pts, void *out,
@@ -500,28 +593,27 @@ int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int
         return fail(PDFX_EINVAL, "pids is NULL");
     if (n_pts < 0)
         return fail(PDFX_EINVAL, "n_pts < 0");
-    if (prec == PDFX_F64 && xfx_lds_bytes(g->ax.n, g->aq.n, false) > device_lds_limit())
-        return fail(PDFX_EINVAL, "grid too large for an FP64 LDS slab; use PDFX_F32S");
-    const void *vals = xf_dev ? xf_dev : (prec == PDFX_F64 ? g->vals64.ptr : g->vals32.ptr);
-    if (!vals)
+    if (!xf_dev && !g->has_values)
         return fail(PDFX_ENOVALUES, "grid has no owned values and xf_dev is NULL");
     if (n_pts > 0 && (!x || !q || !out))
         return fail(PDFX_EINVAL, "x, q2 or out is NULL");
-    const uintptr_t mask = (uintptr_t)7;
-    if (((uintptr_t)x & mask) || ((uintptr_t)q & mask) || ((uintptr_t)vals & 3) ||
-        ((uintptr_t)out & 3))
+    const uintptr_t a8 = (uintptr_t)7, a4 = (uintptr_t)3;
+    if (((uintptr_t)x & a8) || ((uintptr_t)q & a8) || ((uintptr_t)out & a4) ||
+        ((uintptr_t)xf_dev & (prec == PDFX_F64 ? a8 : a4)))
         return fail(PDFX_EINVAL, "misaligned device pointer");
+    *a = XfxArgs{};
     a->ax = g->ax.dev();
     a->aq = g->aq.dev();
-    a->vals = vals;
+    a->vals = g->vals[prec].ptr;
     a->nf = g->nf;
     a->nx = g->ax.n;
     a->nq = g->aq.n;
+    a->slab_elems = g->slab_elems[prec];
+    bool db = false;
+    if (xfx_lds_layout(*a, prec == PDFX_F32S, &db) == 0)
+        return fail(PDFX_EINVAL, "grid too large for an LDS slab in this precision");
     a->n_req = n_req;
-    for (int r = 0; r < kMaxReq; ++r)
-        a->rows[r] = -1;
-    for (int r = 0; r < n_req; ++r)
-        a->rows[r] = g->row_of(pids[r]);
+    plan_columns(g, pids, n_req, a);
     a->x = x;
     a->q = q;
     a->q_is_q = 0;
@@ -532,25 +624,40 @@ int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int
     return PDFX_OK;
 }
 
-int max_resident_blocks(LaunchShape ls, size_t lds, int cus)
+// Repack caller values (if any) and launch the forward kernel.
+int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s)
 {
-    int by_lds = (int)(device_lds_limit() / (lds > 0 ? lds : 1));
-    int by_threads = 2048 / ls.block;
-    int per_cu = by_lds < by_threads ? by_lds : by_threads;
-    if (per_cu < 1)
-        per_cu = 1;
-    return per_cu * cus;
-}
-
-int run_xfx(const pdfx_grid *g, const XfxArgs &a, int prec, hipStream_t s)
-{
-    const LaunchShape ls = g->shape[prec];
+    hipError_t e;
     const bool f32 = prec == PDFX_F32S;
-    const int maxb = max_resident_blocks(ls, xfx_lds_bytes(a.nx, a.nq, f32), g->cus);
-    hipError_t e = f32 ? launch_xfx_f32s(a, ls, maxb, s) : launch_xfx_f64(a, ls, maxb, s);
+    if (xf_dev) {
+        RepackArgs r{xf_dev, g->scratch_vals[prec].ptr, g->nf, a.nx, a.nq, a.slab_elems};
+        if ((e = launch_repack(r, f32, s)) != hipSuccess)
+            return fail_hip(e, "repack launch");
+        a.vals = g->scratch_vals[prec].ptr;
+    }
+    const LaunchShape ls = g->shape[prec];
+    const int maxb = g->max_blocks(prec, a);
+    e = f32 ? launch_xfx_f32s(a, ls, maxb, s) : launch_xfx_f64(a, ls, maxb, s);
     if (e != hipSuccess)
         return fail_hip(e, "xfx launch");
     return PDFX_OK;
 }
 
 }  // namespace pdfx
+
+// Resident workgroups of the current launch shape over the whole device
+// (cached per precision; the persistent kernel never launches more).
+int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a) const
+{
+    const pdfx::LaunchShape ls = shape[prec];
+    if (occ_shape[prec].block == ls.block && occ_shape[prec].ppt == ls.ppt && occ_blocks[prec] > 0)
+        return occ_blocks[prec];
+    int per_cu = 0;
+    hipError_t e = prec == PDFX_F32S ? pdfx::xfx_occupancy_f32s(a, ls, &per_cu)
+                                     : pdfx::xfx_occupancy_f64(a, ls, &per_cu);
+    if (e != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    occ_shape[prec] = ls;
+    occ_blocks[prec] = per_cu * cus;
+    return occ_blocks[prec];
+}

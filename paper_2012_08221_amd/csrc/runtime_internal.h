@@ -42,10 +42,9 @@ int fail(int code, const char *fmt, ...);
 int fail_hip(hipError_t e, const char *what);
 void clear_error();
 int validate_desc(const pdfx_grid_desc *d, bool need_values);
-size_t device_lds_limit();
 int device_cu_count();
 LaunchShape default_shape(bool f32);
-int max_resident_blocks(LaunchShape ls, size_t lds, int cus);
+bool grid_fits_lds(int nx, int nq, int n_as, bool f32);
 
 }  // namespace pdfx
 
@@ -58,11 +57,16 @@ struct pdfx_grid {
     std::vector<int32_t> pids;
     std::vector<int32_t> q_off;
     pdfx::AxisHost ax, aq, aa;
-    pdfx::DeviceBuf vals64, vals32;         // [nf][nx][nq]
-    pdfx::DeviceBuf as_vals64, as_vals32;   // padded [n_as + 2]
-    pdfx::DeviceBuf dom_count;              // unsigned long long
-    pdfx::LaunchShape shape[2];             // per precision
+    int slab_elems[2] = {0, 0};              // per precision
+    pdfx::DeviceBuf vals[2];                 // owned values, bordered slabs, per precision
+    pdfx::DeviceBuf scratch_vals[2];         // bordered copy of caller values, per precision
+    pdfx::DeviceBuf as_vals64, as_vals32;    // padded [n_as + 2]
+    pdfx::DeviceBuf dom_count;               // unsigned long long
+    pdfx::LaunchShape shape[2];              // per precision
+    mutable pdfx::LaunchShape occ_shape[2] = {{0, 0}, {0, 0}};
+    mutable int occ_blocks[2] = {0, 0};
     int row_of(int pid) const;
+    int max_blocks(int prec, const pdfx::XfxArgs &a) const;
 };
 
 namespace pdfx {
@@ -71,6 +75,6 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d);
 int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
                      int32_t n_req, const double *x, const double *q, int64_t n_pts, void *out,
                      int domain_mode, XfxArgs *a);
-int run_xfx(const pdfx_grid *g, const XfxArgs &a, int prec, hipStream_t s);
+int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s);
 
 }  // namespace pdfx

@@ -70,7 +70,7 @@ def test_all_launch_shapes_agree(pdf0, torch, prec):
     keep = pdf0.launch(prec)
     ref = None
     try:
-        shapes = [(256, 1), (256, 2), (256, 4), (512, 2), (512, 4), (1024, 2)]
+        shapes = list(__import__('paper_2012_08221_amd.binding', fromlist=['x']).LAUNCH_SHAPES)
         for blk, ppt in shapes:
             pdf0.set_launch(prec, blk, ppt)
             out = pdf0.xfxQ2(g.pids, xd, qd, prec=prec).cpu().numpy()
