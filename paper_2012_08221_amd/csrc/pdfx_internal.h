@@ -73,6 +73,28 @@ struct XfxArgs {
     int lds_slab0, lds_slab1;     // slab buffer offsets in LDS
 };
 
+struct BwdArgs {
+    AxisDev ax, aq;
+    AxisLds lx, lq;               // LDS layout of the state pass
+    const void *vals;             // bordered slabs (as XfxArgs::vals)
+    int nf, nx, nq, slab_elems;
+    int n_req, n_u;
+    int urow[kMaxReq];
+    int ucol_off[kMaxReq + 1];
+    int ucols[kMaxReq];
+    const double *x, *q;          // q is Q^2
+    int64_t n;
+    int domain_mode;
+    const void *gout;             // [n][n_req] dL/dout, precision's type
+    int32_t *st_idx;              // per point: ix | kq << 16
+    uint8_t *st_flag;             // per point: outside / x clamped / Q^2 clamped
+    double *st_tx, *st_tq;        // per point: FP64 local coordinates
+    double *gacc;                 // [nf][nx][nq] FP64 knot-gradient accumulator, or null
+    double *accx, *accw;          // [n] FP64 sum_r g dxf/dln x, sum_r g dxf/dln Q^2, or null
+    int lds_recx, lds_recq, lds_grad, lds_slab;
+    int chunk;                    // points per workgroup of the adjoint pass
+};
+
 struct AlphasArgs {
     AxisDev a;
     const void *vals;             // padded [n+2] FP64 or FP32: vals[k+1] = alpha_s knot k
@@ -102,6 +124,8 @@ hipError_t xfx_occupancy_f64(const XfxArgs &a, LaunchShape ls, int *blocks_per_c
 hipError_t xfx_occupancy_f32s(const XfxArgs &a, LaunchShape ls, int *blocks_per_cu);
 hipError_t launch_alphas(const AlphasArgs &a, bool f32, hipStream_t s);
 hipError_t launch_repack(const RepackArgs &a, bool f32, hipStream_t s);
+hipError_t launch_backward(const BwdArgs &a, bool f32, void *grad_xf, double *grad_x,
+                           double *grad_q2, int cus, hipStream_t s);
 bool launch_shape_supported(LaunchShape ls);
 int n_launch_shapes();
 LaunchShape launch_shape_at(int i);

@@ -6,13 +6,6 @@ using namespace pdfx;
 
 extern "C" {
 
-int pdfx_eval_xfx_backward(const pdfx_grid *, const void *, int, const int32_t *, int32_t,
-                           const double *, const double *, int64_t, const void *, void *,
-                           double *, double *, int, void *)
-{
-    return fail(PDFX_EINVAL, "pdfx_eval_xfx_backward: not available in this build");
-}
-
 int pdfx_load_set(const pdfx_grid_desc *, int32_t, pdfx_set **out)
 {
     if (out)

@@ -661,3 +661,82 @@ int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a) const
     occ_blocks[prec] = per_cu * cus;
     return occ_blocks[prec];
 }
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+
+extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
+                                      const int32_t *pids, int32_t n_req, const double *x,
+                                      const double *q2, int64_t n_pts, const void *grad_out,
+                                      void *grad_xf, double *grad_x, double *grad_q2,
+                                      int domain_mode, void *stream)
+{
+    using namespace pdfx;
+    clear_error();
+    XfxArgs fa;
+    // grad_out takes the place of `out` in the argument checks
+    int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q2, n_pts,
+                              const_cast<void *>(grad_out), domain_mode, &fa);
+    if (rc != PDFX_OK)
+        return rc;
+    const uintptr_t a8 = 7, a4 = 3;
+    if (((uintptr_t)grad_x & a8) || ((uintptr_t)grad_q2 & a8) ||
+        ((uintptr_t)grad_xf & (prec == PDFX_F64 ? a8 : a4)))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    if (!grad_xf && !grad_x && !grad_q2)
+        return PDFX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    const bool want_coord = grad_x || grad_q2;
+    if (xf_dev && want_coord) {
+        RepackArgs r{xf_dev, g->scratch_vals[prec].ptr, g->nf, fa.nx, fa.nq, fa.slab_elems};
+        if ((e = launch_repack(r, prec == PDFX_F32S, s)) != hipSuccess)
+            return fail_hip(e, "repack launch");
+        fa.vals = g->scratch_vals[prec].ptr;
+    }
+    // workspace: idx, flag, tx, tq, accx, accw per point + the FP64 knot accumulator
+    const int64_t n = n_pts;
+    const size_t nv = (size_t)g->nf * fa.nx * fa.nq;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_idx = 0, o_flag = o_idx + al(4 * n), o_tx = o_flag + al(n),
+                 o_tq = o_tx + al(8 * n), o_ax = o_tq + al(8 * n), o_aw = o_ax + al(8 * n),
+                 o_g = o_aw + al(8 * n), total = o_g + al(8 * nv);
+    if (g->bwd_ws.bytes < total) {
+        if ((e = g->bwd_ws.upload(nullptr, total)) != hipSuccess)
+            return fail_hip(e, "allocate adjoint workspace");
+    }
+    char *ws = (char *)g->bwd_ws.ptr;
+    BwdArgs a{};
+    a.ax = fa.ax;
+    a.aq = fa.aq;
+    a.vals = fa.vals;
+    a.nf = g->nf;
+    a.nx = fa.nx;
+    a.nq = fa.nq;
+    a.slab_elems = fa.slab_elems;
+    a.n_req = n_req;
+    a.n_u = fa.n_u;
+    for (int i = 0; i < kMaxReq; ++i) {
+        a.urow[i] = fa.urow[i];
+        a.ucols[i] = fa.ucols[i];
+    }
+    for (int i = 0; i <= kMaxReq; ++i)
+        a.ucol_off[i] = fa.ucol_off[i];
+    a.x = x;
+    a.q = q2;
+    a.n = n;
+    a.domain_mode = domain_mode;
+    a.gout = grad_out;
+    a.st_idx = (int32_t *)(ws + o_idx);
+    a.st_flag = (uint8_t *)(ws + o_flag);
+    a.st_tx = (double *)(ws + o_tx);
+    a.st_tq = (double *)(ws + o_tq);
+    a.accx = want_coord ? (double *)(ws + o_ax) : nullptr;
+    a.accw = want_coord ? (double *)(ws + o_aw) : nullptr;
+    a.gacc = grad_xf ? (double *)(ws + o_g) : nullptr;
+    e = launch_backward(a, prec == PDFX_F32S, grad_xf, grad_x, grad_q2, g->cus, s);
+    if (e != hipSuccess)
+        return fail_hip(e, "adjoint launch");
+    return PDFX_OK;
+}

@@ -63,6 +63,7 @@ struct pdfx_grid {
     pdfx::DeviceBuf as_vals64, as_vals32;    // padded [n_as + 2]
     pdfx::DeviceBuf dom_count;               // unsigned long long
     pdfx::LaunchShape shape[2];              // per precision
+    mutable pdfx::DeviceBuf bwd_ws;          // adjoint workspace (grows on demand)
     mutable pdfx::LaunchShape occ_shape[2] = {{0, 0}, {0, 0}};
     mutable int occ_blocks[2] = {0, 0};
     int row_of(int pid) const;

@@ -1,0 +1,244 @@
+"""Adjoint (pdfx_eval_xfx_backward / autograd.XfxFunction) against finite
+differences computed by the CPU FP64 oracle.
+
+Knot gradient: central differences with h = 1e-4 on the FP64 upcast of the FP32
+grid, summed pairwise over the points whose stencil touches the knot (the
+loss is linear in the knots, so the difference is exact up to rounding).
+Coordinate gradient: central differences in ln x (step 1e-6) and ln Q^2 (step
+1e-4, see the test), on points whose +-step stays inside one cell.  Metric |g - fd| / max(|fd|, 1e-2 rms(fd)),
+bound 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import cfg0_grid
+from paper_2012_08221_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def mods(torch):
+    from paper_2012_08221_amd import api, autograd
+    return api, autograd
+
+
+def metric(g, fd):
+    g, fd = np.asarray(g, float), np.asarray(fd, float)
+    scale = max(1e-300, 1e-2 * math.sqrt(np.mean(fd ** 2)))
+    return np.abs(g - fd) / np.maximum(np.abs(fd), scale)
+
+
+def touched_mask(grid, loc, f_knot):
+    """Points whose stencil includes knot (i, k) (global Q^2 column k)."""
+    i, k = f_knot
+    ix, s, iq, inside = loc
+    kg = grid.q_off[s] + iq                        # global column of the interval start
+    lo_col = np.maximum(kg - 1, grid.q_off[s])
+    hi_col = np.minimum(kg + 2, grid.q_off[s + 1] - 1)
+    return inside & (ix - 1 <= i) & (i <= ix + 2) & (lo_col <= k) & (k <= hi_col)
+
+
+def fd_knot(grid64, x, q2, loc, w, f, i, k, h=1e-4):
+    """Central FD of sum_p w[p] xf_f(p) w.r.t. v[f][i][k], over touched points."""
+    m = touched_mask(grid64, loc, (i, k))
+    if not m.any():
+        return 0.0, 0
+    gp = wl.GridSpec(pids=grid64.pids, x=grid64.x, q2=grid64.q2, q_off=grid64.q_off,
+                     xf=grid64.xf.copy())
+    gm = wl.GridSpec(pids=grid64.pids, x=grid64.x, q2=grid64.q2, q_off=grid64.q_off,
+                     xf=grid64.xf.copy())
+    gp.xf[f, i, k] += h
+    gm.xf[f, i, k] -= h
+    pid = [int(grid64.pids[f])]
+    up = oracle.xfx(gp, pid, x[m], q2[m])[:, 0]
+    dn = oracle.xfx(gm, pid, x[m], q2[m])[:, 0]
+    return float(np.sum(w[m] * (up - dn)) / (2 * h)), int(m.sum())
+
+
+def cfg3(n=1_000_000):
+    g = cfg0_grid()
+    v32 = g.xf.astype(np.float32)
+    g64 = wl.GridSpec(pids=g.pids, x=g.x, q2=g.q2, q_off=g.q_off, xf=v32.astype(np.float64))
+    x, q2 = wl.queries(3, n)
+    w = wl.loss_weights(3, n)
+    return g, g64, v32, x, q2, w
+
+
+def test_knot_gradient_vs_fd_cfg3(torch, mods):
+    api, ag = mods
+    g, g64, v32, x, q2, w = cfg3()
+    pdf = api.mkPDF(g, with_values=False)
+    vals = torch.as_tensor(v32, device="cuda").requires_grad_(True)
+    xd = torch.as_tensor(x, device="cuda")
+    qd = torch.as_tensor(q2, device="cuda")
+    wd = torch.as_tensor(w, device="cuda").to(torch.float32)
+    y = ag.xfx(pdf, vals, g.pids, xd, qd, prec="f32s")
+    (y * wd).sum().backward()
+    grad = vals.grad.double().cpu().numpy()
+    w = w.astype(np.float32).astype(np.float64)    # the weights the loss was formed with
+    # knots touched by at least one point
+    ix, s, iq, inside = oracle.locate(g, x, q2)
+    touched = np.zeros(grad.shape[1:], dtype=bool)
+    kg = g.q_off[s] + iq
+    for dj in range(-1, 3):
+        for dk in range(-1, 3):
+            ii = ix + dj
+            kk = kg + dk
+            ok = (ii >= 0) & (ii < g.n_x) & (kk >= g.q_off[s]) & (kk < g.q_off[s + 1])
+            touched[ii[ok], kk[ok]] = True
+    # untouched knots: exactly zero gradient
+    assert np.all(grad[:, ~touched] == 0.0)
+    rng = np.random.default_rng(33)
+    cand = np.argwhere(np.broadcast_to(touched, grad.shape))
+    picks = cand[rng.choice(len(cand), 200, replace=False)]
+    errs = []
+    loc = (ix, s, iq, inside)
+    for f, i, k in picks:
+        fd, npts = fd_knot(g64, x, q2, loc, w[:, f], f, i, k)
+        errs.append((grad[f, i, k], fd))
+    gv = np.array(errs)
+    e = metric(gv[:, 0], gv[:, 1])
+    print("knot gradient: max metric %.2e over %d knots" % (e.max(), len(e)))
+    assert e.max() <= TOL
+
+
+def test_knot_gradient_properties(torch, mods):
+    """Independent of the values; sums to sum(w) over all knots (weights sum to 1)."""
+    api, ag = mods
+    g = cfg0_grid()
+    pdf = api.mkPDF(g, with_values=False)
+    n = 200_000
+    x, q2 = wl.queries(5, n)
+    w = wl.loss_weights(5, n)
+    xd, qd = torch.as_tensor(x, device="cuda"), torch.as_tensor(q2, device="cuda")
+    wd = torch.as_tensor(w, device="cuda")
+    grads = []
+    for scale in (1.0, -3.0):
+        vals = (torch.as_tensor(g.xf, device="cuda") * scale).requires_grad_(True)
+        (ag.xfx(pdf, vals, g.pids, xd, qd, prec="f64") * wd).sum().backward()
+        grads.append(vals.grad.cpu().numpy())
+    np.testing.assert_allclose(grads[0], grads[1], rtol=1e-12, atol=1e-9)
+    tot = grads[0].sum(axis=(1, 2))
+    np.testing.assert_allclose(tot, w.sum(axis=0), rtol=1e-9, atol=1e-7)
+
+
+def test_per_point_weight_loss(torch, mods):
+    """The literal loss sum_i w_i xf_a(x_i, Q_i) with one weight per point."""
+    api, ag = mods
+    g, g64, v32, x, q2, _ = cfg3(200_000)
+    wi = wl.loss_weights(3, 200_000, 1)[:, 0]
+    pdf = api.mkPDF(g, with_values=False)
+    vals = torch.as_tensor(v32, device="cuda").requires_grad_(True)
+    xd, qd = torch.as_tensor(x, device="cuda"), torch.as_tensor(q2, device="cuda")
+    y = ag.xfx(pdf, vals, g.pids, xd, qd, prec="f32s")
+    (y * torch.as_tensor(wi, device="cuda").float()[:, None]).sum().backward()
+    grad = vals.grad.double().cpu().numpy()
+    wi = wi.astype(np.float32).astype(np.float64)  # the weights the loss was formed with
+    loc = oracle.locate(g, x, q2)
+    rng = np.random.default_rng(4)
+    out = []
+    for _ in range(40):
+        f = rng.integers(0, 11)
+        i = rng.integers(33, 99)
+        k = rng.integers(5, 49)
+        fd, npts = fd_knot(g64, x, q2, loc, wi, f, i, k)
+        if npts:
+            out.append((grad[f, i, k], fd))
+    a = np.array(out)
+    assert metric(a[:, 0], a[:, 1]).max() <= TOL
+
+
+def test_coordinate_gradient_vs_fd(torch, mods):
+    api, ag = mods
+    g = cfg0_grid()
+    pdf = api.mkPDF(g, with_values=False)
+    n = 20_000
+    x, q2 = wl.queries(6, n)
+    w = wl.loss_weights(6, n)
+    xd = torch.as_tensor(x, device="cuda").requires_grad_(True)
+    qd = torch.as_tensor(q2, device="cuda").requires_grad_(True)
+    vals = torch.as_tensor(g.xf, device="cuda")
+    y = ag.xfx(pdf, vals, g.pids, xd, qd, prec="f64")
+    (y * torch.as_tensor(w, device="cuda")).sum().backward()
+    gx = xd.grad.cpu().numpy() * x          # dL/dln x
+    gq = qd.grad.cpu().numpy() * q2         # dL/dln Q^2
+    # Step per axis: 1e-6 in ln x; 1e-4 in ln Q^2, where the loss depends weakly
+    # on the scale (|dL/dln Q^2| << |L|) and a 1e-6 step is rounding-limited
+    # (inside one cell the interpolant is a cubic, so the step costs O(h^2)).
+    loc = oracle.locate(g, x, q2)
+    for coord, gval in (("x", gx), ("q", gq)):
+        h = 1e-6 if coord == "x" else 1e-4
+        if coord == "x":
+            xp, xm, qp, qm = x * math.exp(h), x * math.exp(-h), q2, q2
+        else:
+            xp, xm, qp, qm = x, x, q2 * math.exp(h), q2 * math.exp(-h)
+        lp, lm = oracle.locate(g, xp, qp), oracle.locate(g, xm, qm)
+        same = np.all([(a == b) & (a == c) for a, b, c in zip(loc[:3], lp[:3], lm[:3])], axis=0)
+        same &= lp[3] & lm[3]
+        up = np.sum(w * oracle.xfx(g, g.pids, xp, qp), axis=1)
+        dn = np.sum(w * oracle.xfx(g, g.pids, xm, qm), axis=1)
+        fd = (up - dn) / (2 * h)
+        e = metric(gval[same], fd[same])
+        print("d/dln %s: max metric %.2e over %d points (%d excluded)" %
+              (coord, e.max(), same.sum(), (~same).sum()))
+        assert same.sum() > 0.9 * n
+        assert e.max() <= TOL
+
+
+def test_backward_domain_semantics(torch, mods):
+    api, ag = mods
+    g = cfg0_grid()
+    pdf = api.mkPDF(g, with_values=False)
+    x = np.array([0.1, 1e-10, 0.1, 0.2])
+    q2 = np.array([100.0, 100.0, 1e12, 50.0])
+    vals = torch.as_tensor(g.xf, device="cuda")
+    for domain in ("nan", "clamp"):
+        xd = torch.as_tensor(x, device="cuda").requires_grad_(True)
+        qd = torch.as_tensor(q2, device="cuda").requires_grad_(True)
+        v = vals.clone().requires_grad_(True)
+        y = ag.xfx(pdf, v, [21, 2], xd, qd, prec="f64", domain=domain)
+        y.sum().backward()
+        gx, gq = xd.grad.cpu().numpy(), qd.grad.cpu().numpy()
+        if domain == "nan":
+            assert np.all(np.isnan(gx[1:3])) and np.all(np.isnan(gq[1:3]))
+            assert np.all(np.isfinite(gx[[0, 3]]))
+            # out-of-grid points leave no trace in the knot gradient
+            v2 = vals.clone().requires_grad_(True)
+            ag.xfx(pdf, v2, [21, 2], torch.as_tensor(x[[0, 3]], device="cuda"),
+                   torch.as_tensor(q2[[0, 3]], device="cuda"), prec="f64").sum().backward()
+            np.testing.assert_allclose(v.grad.cpu().numpy(), v2.grad.cpu().numpy(),
+                                       rtol=1e-13, atol=1e-15)
+        else:
+            assert gx[1] == 0.0 and gq[2] == 0.0
+            assert np.isfinite(gq[1]) and np.isfinite(gx[2])
+    pdf.domain_errors()
+
+
+def test_gradcheck_tiny_fp64(torch, mods):
+    api, ag = mods
+    rng = np.random.default_rng(8)
+    xk = np.exp(np.linspace(math.log(1e-3), 0, 6))
+    qk = np.exp(np.linspace(0, 5, 7))
+    g = wl.GridSpec(pids=np.array([21, 1], np.int32), x=xk, q2=qk,
+                    q_off=np.array([0, 7], np.int32), xf=rng.standard_normal((2, 6, 7)))
+    pdf = api.mkPDF(g, with_values=False)
+    xq = np.exp(rng.uniform(math.log(1e-3), -0.01, 12))
+    qq = np.exp(rng.uniform(0.01, 4.99, 12))
+    v = torch.as_tensor(g.xf, device="cuda").requires_grad_(True)
+    xd = torch.as_tensor(xq, device="cuda").requires_grad_(True)
+    qd = torch.as_tensor(qq, device="cuda").requires_grad_(True)
+    f = lambda v_, x_, q_: ag.xfx(pdf, v_, [21, 1], x_, q_, prec="f64")  # noqa: E731
+    assert torch.autograd.gradcheck(f, (v, xd, qd), eps=1e-7, atol=1e-6, rtol=1e-5)
