@@ -142,3 +142,39 @@ class PDF:
 def mkPDF(spec, with_values: bool = True) -> PDF:
     """Build a PDF object for one member (the paper's mkPDF, Sec. 2.1)."""
     return PDF(spec, with_values)
+
+
+class PDFSet:
+    """Many members (uneven grids, shared pid list) evaluated in one launch."""
+
+    def __init__(self, specs):
+        self._descs = [B.HostDesc(s.pids, s.x, s.q2, s.q_off, s.xf) for s in specs]
+        self.handle = B.pdfx_load_set(self._descs)
+        self.n_mem = len(specs)
+        self.pids = np.array(specs[0].pids, dtype=np.int32)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.pdfx_free_set(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def xfxQ2(self, pids, x, q2, prec="f64", domain="nan", out=None):
+        """x f of every member -> [n_mem, n, len(pids)]."""
+        x = _device_f64(x)
+        q2 = _device_f64(q2, x.device)
+        pids = np.atleast_1d(np.asarray(pids, dtype=np.int32))
+        n = x.numel()
+        if out is None:
+            out = torch.empty((self.n_mem, n, pids.shape[0]), dtype=prec_dtype(prec), device=x.device)
+        B.pdfx_eval_set_xfx(self.handle, prec_code(prec), pids, x.data_ptr(), q2.data_ptr(), n,
+                            out.data_ptr(), _DOMAIN[domain], _stream(x.device))
+        return out
+
+    def autotune(self, prec="f64", n_req=None, n_pts=1 << 20, cache_path=None):
+        B.pdfx_autotune_set(self.handle, prec_code(prec), n_req or len(self.pids), n_pts, cache_path)

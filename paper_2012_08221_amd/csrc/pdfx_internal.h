@@ -95,6 +95,33 @@ struct BwdArgs {
     int chunk;                    // points per workgroup of the adjoint pass
 };
 
+// One member of a set on the device.
+struct MemberDev {
+    AxisDev ax, aq;
+    const void *vals64, *vals32;  // bordered slabs per precision
+    int nx, nq, slab64, slab32;   // slab elements per precision
+};
+
+struct SetArgs {
+    const MemberDev *mem;         // [n_mem] on the device
+    int n_mem;
+    int n_req, n_u;
+    int urow[kMaxReq];
+    int ucol_off[kMaxReq + 1];
+    int ucols[kMaxReq];
+    int n_zero;
+    int zcols[kMaxReq];
+    const double *x, *q;          // shared points, q = Q^2
+    int64_t n;
+    void *out;                    // [n_mem][n][n_req]
+    int domain_mode;
+    unsigned long long *dom_count;
+    unsigned int *counter;        // work-list cursor (reset before each launch)
+    int n_items, items_per_member, tiles_per_item;
+    AxisLds lx, lq;               // LDS offsets, sized for the largest member
+    int lds_slab;
+};
+
 struct AlphasArgs {
     AxisDev a;
     const void *vals;             // padded [n+2] FP64 or FP32: vals[k+1] = alpha_s knot k
@@ -126,6 +153,10 @@ hipError_t launch_alphas(const AlphasArgs &a, bool f32, hipStream_t s);
 hipError_t launch_repack(const RepackArgs &a, bool f32, hipStream_t s);
 hipError_t launch_backward(const BwdArgs &a, bool f32, void *grad_xf, double *grad_x,
                            double *grad_q2, int cus, hipStream_t s);
+hipError_t launch_set(const SetArgs &a, bool f32, LaunchShape ls, size_t lds, int cus, hipStream_t s);
+bool set_shape_supported(LaunchShape ls);
+int n_set_shapes();
+LaunchShape set_shape_at(int i);
 bool launch_shape_supported(LaunchShape ls);
 int n_launch_shapes();
 LaunchShape launch_shape_at(int i);

@@ -740,3 +740,170 @@ extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, in
         return fail_hip(e, "adjoint launch");
     return PDFX_OK;
 }
+
+// ---------------------------------------------------------------------------
+// sets of members
+// ---------------------------------------------------------------------------
+
+pdfx_set::~pdfx_set()
+{
+    for (auto *g : members)
+        delete g;
+}
+
+namespace pdfx {
+
+// LDS layout of the set kernel for the largest member; 0 if it does not fit.
+static size_t set_lds_layout(const pdfx_set *s, bool f32, SetArgs *a)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes, size_t align) {
+        off = (off + align - 1) / align * align;
+        const size_t r = off;
+        off += bytes;
+        return (int)r;
+    };
+    a->lx.knots = take((size_t)s->max_nx * 8, 16);
+    a->lx.seed = take((size_t)s->max_nbx * 2, 16);
+    a->lx.rec64 = take((size_t)(s->max_nx - 1) * 64, 64);
+    a->lx.rec32 = take(f32 ? (size_t)(s->max_nx - 1) * 32 : 0, 64);
+    a->lq.knots = take((size_t)s->max_nq * 8, 16);
+    a->lq.seed = take((size_t)s->max_nbq * 2, 16);
+    a->lq.rec64 = take((size_t)(s->max_nq - 1) * 64, 64);
+    a->lq.rec32 = take(f32 ? (size_t)(s->max_nq - 1) * 32 : 0, 64);
+    a->lds_slab = take(s->max_slab[f32 ? PDFX_F32S : PDFX_F64], 16);
+    // the kernel's own static __shared__ word sits beside the dynamic region
+    return off + 16 <= kLdsLimit ? off : 0;
+}
+
+}  // namespace pdfx
+
+extern "C" {
+
+int pdfx_load_set(const pdfx_grid_desc *members, int32_t n_mem, pdfx_set **out)
+{
+    using namespace pdfx;
+    clear_error();
+    if (!out)
+        return fail(PDFX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!members || n_mem < 1 || n_mem > 100000)
+        return fail(PDFX_EINVAL, "need 1..100000 member descriptors");
+    for (int m = 0; m < n_mem; ++m) {
+        int rc = validate_desc(&members[m], true);
+        if (rc != PDFX_OK)
+            return fail(rc, "member %d: %s", m, pdfx_last_error());
+        if (members[m].n_flav != members[0].n_flav)
+            return fail(PDFX_EINVAL, "member %d: flavour count differs from member 0", m);
+        for (int f = 0; f < members[0].n_flav; ++f)
+            if (members[m].pids[f] != members[0].pids[f])
+                return fail(PDFX_EINVAL, "member %d: pid list differs from member 0", m);
+    }
+    pdfx_set *s = new pdfx_set();
+    s->pids.assign(members[0].pids, members[0].pids + members[0].n_flav);
+    std::vector<MemberDev> md(n_mem);
+    for (int m = 0; m < n_mem; ++m) {
+        pdfx_grid *g = new pdfx_grid();
+        s->members.push_back(g);
+        pdfx_grid_desc d = members[m];
+        d.n_as = 0;  // alpha_s is not part of a set evaluation
+        int rc = grid_init(g, &d);
+        if (rc != PDFX_OK) {
+            delete s;
+            return rc;
+        }
+        md[m].ax = g->ax.dev();
+        md[m].aq = g->aq.dev();
+        md[m].vals64 = g->vals[PDFX_F64].ptr;
+        md[m].vals32 = g->vals[PDFX_F32S].ptr;
+        md[m].nx = g->ax.n;
+        md[m].nq = g->aq.n;
+        md[m].slab64 = g->slab_elems[PDFX_F64];
+        md[m].slab32 = g->slab_elems[PDFX_F32S];
+        s->max_nx = std::max(s->max_nx, g->ax.n);
+        s->max_nq = std::max(s->max_nq, g->aq.n);
+        s->max_nbx = std::max(s->max_nbx, g->ax.nbuckets);
+        s->max_nbq = std::max(s->max_nbq, g->aq.nbuckets);
+        s->max_slab[PDFX_F64] = std::max(s->max_slab[PDFX_F64], (size_t)md[m].slab64 * 8);
+        s->max_slab[PDFX_F32S] = std::max(s->max_slab[PDFX_F32S], (size_t)md[m].slab32 * 4);
+    }
+    SetArgs probe{};
+    if (set_lds_layout(s, true, &probe) == 0) {
+        delete s;
+        return fail(PDFX_EINVAL, "the largest member does not fit one LDS slab");
+    }
+    hipError_t e;
+    if ((e = s->mem_desc.upload(md.data(), md.size() * sizeof(MemberDev))) != hipSuccess ||
+        (e = s->counter.upload(nullptr, 256)) != hipSuccess ||
+        (e = s->dom_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess) {
+        delete s;
+        return fail_hip(e, "upload set descriptors");
+    }
+    s->cus = device_cu_count();
+    *out = s;
+    return PDFX_OK;
+}
+
+void pdfx_free_set(pdfx_set *s) { delete s; }
+
+int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t n_req,
+                      const double *x, const double *q2, int64_t n_pts, void *out,
+                      int domain_mode, void *stream)
+{
+    using namespace pdfx;
+    clear_error();
+    if (!s)
+        return fail(PDFX_EINVAL, "set is NULL");
+    // argument checks and the column plan, as for one member
+    XfxArgs fa;
+    const pdfx_grid *g0 = s->members[0];
+    int rc = prepare_xfx_args(g0, nullptr, prec == PDFX_F64 ? PDFX_F32S : prec, pids, n_req, x,
+                              q2, n_pts, out, domain_mode, &fa);
+    if (rc != PDFX_OK)
+        return rc;
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    if (n_pts == 0)
+        return PDFX_OK;
+    SetArgs a{};
+    const size_t lds = set_lds_layout(s, prec == PDFX_F32S, &a);
+    if (lds == 0)
+        return fail(PDFX_EINVAL, "the largest member does not fit LDS in this precision");
+    a.mem = (const MemberDev *)s->mem_desc.ptr;
+    a.n_mem = (int)s->members.size();
+    a.n_req = n_req;
+    a.n_u = fa.n_u;
+    a.n_zero = fa.n_zero;
+    for (int i = 0; i < kMaxReq; ++i) {
+        a.urow[i] = fa.urow[i];
+        a.ucols[i] = fa.ucols[i];
+        a.zcols[i] = fa.zcols[i];
+    }
+    for (int i = 0; i <= kMaxReq; ++i)
+        a.ucol_off[i] = fa.ucol_off[i];
+    a.x = x;
+    a.q = q2;
+    a.n = n_pts;
+    a.out = out;
+    a.domain_mode = domain_mode;
+    a.dom_count = (unsigned long long *)s->dom_count.ptr;
+    a.counter = (unsigned int *)s->counter.ptr;
+    const LaunchShape ls = s->shape[prec];
+    const int64_t tile_pts = (int64_t)ls.block * ls.ppt;
+    const int64_t ntiles = (n_pts + tile_pts - 1) / tile_pts;
+    int64_t tpi = s->tiles_per_item[prec];
+    if (tpi < 1)
+        tpi = 1;
+    const int64_t ipm = (ntiles + tpi - 1) / tpi;
+    if ((int64_t)a.n_mem * ipm > 0x7fffffff)
+        return fail(PDFX_EINVAL, "work list too long");
+    a.tiles_per_item = (int)tpi;
+    a.items_per_member = (int)ipm;
+    a.n_items = (int)(a.n_mem * ipm);
+    hipError_t e = launch_set(a, prec == PDFX_F32S, ls, lds, s->cus, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "set launch");
+    return PDFX_OK;
+}
+
+}  // extern "C"

@@ -79,3 +79,17 @@ int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int
 int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s);
 
 }  // namespace pdfx
+
+struct pdfx_set {
+    std::vector<pdfx_grid *> members;
+    std::vector<int32_t> pids;               // shared by every member
+    pdfx::DeviceBuf mem_desc;                // MemberDev[n_mem]
+    pdfx::DeviceBuf counter;                 // work-list cursor
+    pdfx::DeviceBuf dom_count;
+    int max_nx = 0, max_nq = 0, max_nbx = 0, max_nbq = 0;
+    size_t max_slab[2] = {0, 0};             // bytes per precision
+    pdfx::LaunchShape shape[2] = {{512, 2}, {512, 2}};
+    int tiles_per_item[2] = {4, 4};
+    int cus = 256;
+    ~pdfx_set();
+};

@@ -1,0 +1,118 @@
+"""Many members in one persistent launch (pdfx_eval_set_xfx) against the oracle:
+101 replica-style members with uneven grids; every member on 1e4 points, and a
+few members on 1e6 shared points (sampled)."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import capped_rel_err, f32_tolerance
+from paper_2012_08221_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def members():
+    return wl.member_grids(101)
+
+
+@pytest.fixture(scope="module")
+def pset(torch, members):
+    from paper_2012_08221_amd import api
+    return api.PDFSet(members)
+
+
+def check_member(m, got, x, q2, pids, prec):
+    ora = oracle.xfx(m, pids, x, q2)
+    M = oracle.stencil_absmax(m, pids, x, q2)
+    np.testing.assert_array_equal(np.isnan(got), np.isnan(ora))
+    ok = ~np.isnan(ora)
+    e = capped_rel_err(got[ok], ora[ok], M[ok])
+    tol = 1e-12 if prec == "f64" else f32_tolerance(m)
+    return e.max() if e.size else 0.0, tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_all_members_small(pset, members, prec):
+    x, q2 = wl.queries(2, 10_000)
+    pids = members[0].pids
+    out = pset.xfxQ2(pids, x, q2, prec=prec).double().cpu().numpy()
+    assert out.shape == (101, 10_000, 11)
+    worst = 0.0
+    for k, m in enumerate(members):
+        e, tol = check_member(m, out[k], x, q2, pids, prec)
+        worst = max(worst, e)
+        assert e <= tol, (k, e, tol)
+    print("101 members x 1e4 points, %s: worst %.2e" % (prec, worst))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_few_members_full_points_sampled(pset, members, torch, prec):
+    n = 1_000_000
+    x, q2 = wl.queries(2, n)
+    xd, qd = torch.as_tensor(x, device="cuda"), torch.as_tensor(q2, device="cuda")
+    out = pset.xfxQ2(members[0].pids, xd, qd, prec=prec)
+    idx = np.random.default_rng(1).choice(n, 20_000, replace=False)
+    sel = out[:, torch.as_tensor(idx, device="cuda")].double().cpu().numpy()
+    for k in (0, 1, 50, 99, 100):
+        e, tol = check_member(members[k], sel[k], x[idx], q2[idx], members[0].pids, prec)
+        assert e <= tol, (k, e)
+    assert bool(torch.isfinite(out).all())
+
+
+def test_shapes_and_work_split_agree(pset, members, tmp_path):
+    """Every compiled set shape and several work splits give the same result:
+    each (shape, tiles per item) is forced through a tuning-cache entry."""
+    from paper_2012_08221_amd import binding as B
+    x, q2 = wl.queries(9, 30_001)
+    ref = None
+    cache = tmp_path / "tune.jsonl"
+    pset.autotune("f64", n_req=3, n_pts=30_001, cache_path=str(cache))
+    key_line = cache.read_text().strip().splitlines()[-1]
+    key = key_line.split('"key": "')[1].split('"')[0]
+    for blk, ppt in ((256, 4), (512, 2), (1024, 1)):
+        for tpi in (1, 3):
+            with open(cache, "a") as fh:
+                fh.write('{"key": "%s", "block": %d, "ppt": %d, "tpi": %d, "ms": 0}\n'
+                         % (key, blk, ppt, tpi))
+            B.pdfx_autotune_set(pset.handle, B.PDFX_F64, 3, 30_001, str(cache))
+            out = pset.xfxQ2([21, 2, -3], x, q2).cpu().numpy()
+            if ref is None:
+                ref = out
+            np.testing.assert_array_equal(out, ref)
+    for k in (0, 7, 100):
+        e, tol = check_member(members[k], ref[k], x, q2, [21, 2, -3], "f64")
+        assert e <= tol
+
+
+def test_one_member_set_matches_single_grid(torch, members):
+    from paper_2012_08221_amd import api
+    m = members[3]
+    s1 = api.PDFSet([m])
+    g1 = api.mkPDF(m)
+    x, q2 = wl.queries(4, 50_000)
+    for prec in ("f64", "f32s"):
+        a = s1.xfxQ2(m.pids, x, q2, prec=prec)[0].cpu().numpy()
+        b = g1.xfxQ2(m.pids, x, q2, prec=prec).cpu().numpy()
+        np.testing.assert_array_equal(a, b)
+
+
+def test_set_domain_and_pid_requests(pset, members):
+    x = np.array([0.1, 1e-12, 0.3])
+    q2 = np.array([50.0, 50.0, 1e11])
+    out = pset.xfxQ2([21, 7, 1], x, q2, domain="nan").cpu().numpy()
+    assert np.all(np.isfinite(out[:, 0, [0, 2]])) and np.all(out[:, :, 1] == 0)
+    assert np.all(np.isnan(out[:, 1:, 0]))
+    outc = pset.xfxQ2([21], x, q2, domain="clamp").cpu().numpy()
+    assert np.all(np.isfinite(outc))
+    for k in (0, 60):
+        ora = oracle.xfx(members[k], [21], x, q2, mode=1)
+        np.testing.assert_allclose(outc[k], ora, rtol=1e-12)
