@@ -178,3 +178,27 @@ class PDFSet:
 
     def autotune(self, prec="f64", n_req=None, n_pts=1 << 20, cache_path=None):
         B.pdfx_autotune_set(self.handle, prec_code(prec), n_req or len(self.pids), n_pts, cache_path)
+
+
+def dy_integrand(pdf, u1, u2, xmin=1e-5, s=13000.0 ** 2, prec="f64", values=None, out=True):
+    """Per-point LO Drell-Yan-like integrand I(u1, u2) (pdfx_eval_dy) and the
+    per-workgroup FP64 partial sums of I.  Returns (I or None, partial sums)."""
+    u1 = _device_f64(u1)
+    u2 = _device_f64(u2, u1.device)
+    n = u1.numel()
+    res = torch.empty(n, dtype=prec_dtype(prec), device=u1.device) if out else None
+    sums = torch.empty(B.pdfx_dy_max_blocks(), dtype=torch.float64, device=u1.device)
+    nb = B.pdfx_eval_dy(pdf.handle, _ptr(values), prec_code(prec), u1.data_ptr(), u2.data_ptr(),
+                        n, xmin, s, _ptr(res), sums.data_ptr(), _stream(u1.device))
+    return res, sums[:nb]
+
+
+def dy_backward(pdf, u1, u2, grad_xf, xmin=1e-5, s=13000.0 ** 2, scale=1.0, prec="f64",
+                values=None):
+    """grad_xf += scale * d(sum_p I_p)/d(knot values) (pdfx_eval_dy_backward)."""
+    u1 = _device_f64(u1)
+    u2 = _device_f64(u2, u1.device)
+    B.pdfx_eval_dy_backward(pdf.handle, _ptr(values), prec_code(prec), u1.data_ptr(),
+                            u2.data_ptr(), u1.numel(), xmin, s, scale, grad_xf.data_ptr(),
+                            _stream(u1.device))
+    return grad_xf

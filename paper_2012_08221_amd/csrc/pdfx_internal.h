@@ -122,6 +122,32 @@ struct SetArgs {
     int lds_slab;
 };
 
+// Drell-Yan-like integrand (forward and backward).
+constexpr int kDyMaxBlocks = 4096;
+struct DyArgs {
+    AxisDev ax, aq, aa;           // x, Q^2 and alpha_s axes
+    AxisLds lx, lq, la;
+    int lds_asv;                  // padded alpha_s values in LDS
+    const void *as_vals;          // padded alpha_s values, precision's type
+    const double *as_vals64;      // padded alpha_s values, FP64 (backward state pass)
+    const void *vals;             // bordered slabs
+    int nf, nx, nq, slab_elems;
+    int n_seq;                    // flavours in the sequence q, -q, q', -q', ...
+    int seq_row[10];              // their grid rows
+    const double *u1, *u2;
+    int64_t n;
+    double lnxmin, lnrange, s, L2, scale;
+    void *out;                    // [n] or null
+    double *block_sums;           // [grid] or null
+    unsigned long long *dom_count;
+    int lds_slab0, lds_slab1;
+    int32_t *st_i1, *st_i2;       // backward state: x1 bin | Q^2 bin << 16 (-1: skip), x2 bin
+    double *st_t1, *st_t2, *st_tq, *st_as;
+    double *gacc;                 // [nf][nx][nq] FP64
+    int lds_recx, lds_recq, lds_grad;
+    int chunk;
+};
+
 struct AlphasArgs {
     AxisDev a;
     const void *vals;             // padded [n+2] FP64 or FP32: vals[k+1] = alpha_s knot k
@@ -154,6 +180,9 @@ hipError_t launch_repack(const RepackArgs &a, bool f32, hipStream_t s);
 hipError_t launch_backward(const BwdArgs &a, bool f32, void *grad_xf, double *grad_x,
                            double *grad_q2, int cus, hipStream_t s);
 hipError_t launch_set(const SetArgs &a, bool f32, LaunchShape ls, size_t lds, int cus, hipStream_t s);
+hipError_t launch_dy_forward(const DyArgs &a, bool f32, int cus, hipStream_t s, int *n_blocks);
+hipError_t launch_dy_backward(const DyArgs &a, bool f32, void *grad_xf, int cus, hipStream_t s);
+size_t dy_lds_layout(DyArgs &a, bool f32, bool *db);
 bool set_shape_supported(LaunchShape ls);
 int n_set_shapes();
 LaunchShape set_shape_at(int i);

@@ -907,3 +907,141 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Drell-Yan-like integrand
+// ---------------------------------------------------------------------------
+
+namespace pdfx {
+
+static int prepare_dy(const pdfx_grid *g, const void *xf_dev, int prec, const double *u1,
+                      const double *u2, int64_t n, double xmin, double s, DyArgs *a,
+                      hipStream_t stream)
+{
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    if (!g->has_alphas)
+        return fail(PDFX_ENOALPHAS, "the integrand needs alpha_s knots");
+    if (!xf_dev && !g->has_values)
+        return fail(PDFX_ENOVALUES, "grid has no owned values and xf_dev is NULL");
+    if (n < 0)
+        return fail(PDFX_EINVAL, "n < 0");
+    if (n > 0 && (!u1 || !u2))
+        return fail(PDFX_EINVAL, "u1 or u2 is NULL");
+    if (((uintptr_t)u1 & 7) || ((uintptr_t)u2 & 7))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    if (!(xmin > 0.0 && xmin < 1.0) || !(s > 0.0) || !std::isfinite(s))
+        return fail(PDFX_EINVAL, "need 0 < xmin < 1 and s > 0");
+    *a = DyArgs{};
+    a->ax = g->ax.dev();
+    a->aq = g->aq.dev();
+    a->aa = g->aa.dev();
+    a->as_vals = prec == PDFX_F64 ? g->as_vals64.ptr : g->as_vals32.ptr;
+    a->as_vals64 = (const double *)g->as_vals64.ptr;
+    a->vals = g->vals[prec].ptr;
+    a->nf = g->nf;
+    a->nx = g->ax.n;
+    a->nq = g->aq.n;
+    a->slab_elems = g->slab_elems[prec];
+    bool db = false;
+    if (dy_lds_layout(*a, prec == PDFX_F32S, &db) == 0)
+        return fail(PDFX_EINVAL, "grid too large for an LDS slab in this precision");
+    a->n_seq = 0;
+    for (int q = 1; q <= 5; ++q) {
+        const int rq = g->row_of(q), rqb = g->row_of(-q);
+        if (rq < 0 || rqb < 0)
+            continue;   // an absent parton contributes 0
+        a->seq_row[a->n_seq++] = rq;
+        a->seq_row[a->n_seq++] = rqb;
+    }
+    a->u1 = u1;
+    a->u2 = u2;
+    a->n = n;
+    a->lnxmin = std::log(xmin);
+    a->lnrange = std::log(1.0 / xmin);
+    a->s = s;
+    a->L2 = a->lnrange * a->lnrange;
+    a->dom_count = (unsigned long long *)g->dom_count.ptr;
+    if (xf_dev && n > 0) {
+        RepackArgs r{xf_dev, g->scratch_vals[prec].ptr, g->nf, a->nx, a->nq, a->slab_elems};
+        hipError_t e = launch_repack(r, prec == PDFX_F32S, stream);
+        if (e != hipSuccess)
+            return fail_hip(e, "repack launch");
+        a->vals = g->scratch_vals[prec].ptr;
+    }
+    return PDFX_OK;
+}
+
+}  // namespace pdfx
+
+extern "C" {
+
+int32_t pdfx_dy_max_blocks(void) { return pdfx::kDyMaxBlocks; }
+
+int pdfx_eval_dy(const pdfx_grid *g, const void *xf_dev, int prec, const double *u1,
+                 const double *u2, int64_t n, double xmin, double s, void *out,
+                 double *block_sums, int32_t *n_blocks, void *stream)
+{
+    using namespace pdfx;
+    clear_error();
+    if (n_blocks)
+        *n_blocks = 0;
+    DyArgs a;
+    int rc = prepare_dy(g, xf_dev, prec, u1, u2, n, xmin, s, &a, (hipStream_t)stream);
+    if (rc != PDFX_OK || n == 0)
+        return rc;
+    if (((uintptr_t)out & 3) || ((uintptr_t)block_sums & 7))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    a.out = out;
+    a.block_sums = block_sums;
+    int nb = 0;
+    hipError_t e = launch_dy_forward(a, prec == PDFX_F32S, g->cus, (hipStream_t)stream, &nb);
+    if (e != hipSuccess)
+        return fail_hip(e, "integrand launch");
+    if (n_blocks)
+        *n_blocks = nb;
+    return PDFX_OK;
+}
+
+int pdfx_eval_dy_backward(const pdfx_grid *g, const void *xf_dev, int prec, const double *u1,
+                          const double *u2, int64_t n, double xmin, double s, double scale,
+                          void *grad_xf, void *stream)
+{
+    using namespace pdfx;
+    clear_error();
+    DyArgs a;
+    int rc = prepare_dy(g, xf_dev, prec, u1, u2, n, xmin, s, &a, (hipStream_t)stream);
+    if (rc != PDFX_OK)
+        return rc;
+    if (!grad_xf)
+        return fail(PDFX_EINVAL, "grad_xf is NULL");
+    if ((uintptr_t)grad_xf & (prec == PDFX_F64 ? 7 : 3))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    if (n == 0)
+        return PDFX_OK;
+    a.scale = scale;
+    const size_t nv = (size_t)g->nf * a.nx * a.nq;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_i1 = 0, o_i2 = o_i1 + al(4 * n), o_t1 = o_i2 + al(4 * n), o_t2 = o_t1 + al(8 * n),
+                 o_tq = o_t2 + al(8 * n), o_as = o_tq + al(8 * n), o_g = o_as + al(8 * n),
+                 total = o_g + al(8 * nv);
+    hipError_t e;
+    if (g->bwd_ws.bytes < total && (e = g->bwd_ws.upload(nullptr, total)) != hipSuccess)
+        return fail_hip(e, "allocate integrand workspace");
+    char *ws = (char *)g->bwd_ws.ptr;
+    a.st_i1 = (int32_t *)(ws + o_i1);
+    a.st_i2 = (int32_t *)(ws + o_i2);
+    a.st_t1 = (double *)(ws + o_t1);
+    a.st_t2 = (double *)(ws + o_t2);
+    a.st_tq = (double *)(ws + o_tq);
+    a.st_as = (double *)(ws + o_as);
+    a.gacc = (double *)(ws + o_g);
+    e = launch_dy_backward(a, prec == PDFX_F32S, grad_xf, g->cus, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "integrand backward launch");
+    return PDFX_OK;
+}
+
+}  // extern "C"

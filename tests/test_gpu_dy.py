@@ -1,0 +1,143 @@
+"""Fused LO Drell-Yan-like integrand (pdfx_eval_dy / pdfx_eval_dy_backward)
+against the CPU FP64 oracle: per-point values, partial sums, and the knot
+gradient of sum_p I_p against oracle finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import cfg0_grid
+from paper_2012_08221_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+XMIN = wl.DY_XMIN
+S = wl.SQRT_S_DY ** 2
+L = math.log(1.0 / XMIN)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def api(torch):
+    from paper_2012_08221_amd import api as a
+    return a
+
+
+@pytest.fixture(scope="module")
+def pdf(api):
+    return api.mkPDF(cfg0_grid())
+
+
+def kinematics(grid, u1, u2):
+    x1 = np.exp(math.log(XMIN) + u1 * L)
+    x2 = np.exp(math.log(XMIN) + u2 * L)
+    q2 = np.clip(x1 * x2 * S, grid.q2[0], grid.q2[-1])
+    return x1, x2, q2
+
+
+def scale_of(grid, u1, u2):
+    """Error scale: L^2 alpha_s sum_q M_q(x1) M_-q(x2), M = stencil max |v|."""
+    x1, x2, q2 = kinematics(grid, u1, u2)
+    m1 = oracle.stencil_absmax(grid, [1, 2, 3, 4, 5], x1, q2)
+    m2 = oracle.stencil_absmax(grid, [-1, -2, -3, -4, -5], x2, q2)
+    a = oracle.alphas(grid.as_q2, grid.as_val, q2)
+    return L * L * a * np.sum(m1 * m2, axis=1)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32s", 1e-5)])
+def test_integrand_parity_chunk0(pdf, prec, tol):
+    g = cfg0_grid()
+    u1, u2 = wl.dy_uniforms(0, 1_000_000)
+    got, sums = pdf_dy(pdf, u1, u2, prec)
+    ora = oracle.dy(g, u1, u2, XMIN, S)
+    sc = scale_of(g, u1, u2)
+    e = np.abs(got - ora) / np.maximum(np.abs(ora), 0.1 * sc)
+    print("integrand %s: max err %.2e; clipped at Q2_min: %.1f%%" %
+          (prec, e.max(), 100 * np.mean(kinematics(g, u1, u2)[2] == g.q2[0])))
+    assert e.max() <= tol
+    rel = abs(sums.sum() - ora.sum()) / np.abs(ora).sum()
+    assert rel <= (1e-12 if prec == "f64" else 1e-6)
+
+
+def pdf_dy(pdf, u1, u2, prec, values=None):
+    from paper_2012_08221_amd import api
+    res, sums = api.dy_integrand(pdf, u1, u2, XMIN, S, prec=prec, values=values)
+    return res.double().cpu().numpy(), sums.cpu().numpy()
+
+
+def test_integrand_edges(pdf, api, torch):
+    res, sums = api.dy_integrand(pdf, np.zeros(0), np.zeros(0))
+    assert res.numel() == 0 and sums.numel() == 0
+    u1, u2 = wl.dy_uniforms(1, 777)
+    u1[:3] = [0.0, 0.999999999, 0.5]
+    u2[:3] = [0.0, 0.999999999, 0.0]
+    got, sums = pdf_dy(pdf, u1, u2, "f64")
+    ora = oracle.dy(cfg0_grid(), u1, u2, XMIN, S)
+    np.testing.assert_allclose(got, ora, rtol=1e-12, atol=1e-12 * np.abs(ora).max())
+    only_sums, sums2 = api.dy_integrand(pdf, u1, u2, out=False)
+    assert only_sums is None
+    np.testing.assert_allclose(sums2.cpu().numpy().sum(), ora.sum(), rtol=1e-12)
+    v = torch.as_tensor(cfg0_grid().xf, device="cuda")
+    got2, _ = pdf_dy(pdf, u1, u2, "f64", values=v)
+    np.testing.assert_array_equal(got, got2)
+
+
+def touched(grid, x, q2, i, k):
+    ix, s, iq, inside = oracle.locate(grid, x, q2)
+    kg = grid.q_off[s] + iq
+    lo = np.maximum(kg - 1, grid.q_off[s])
+    hi = np.minimum(kg + 2, grid.q_off[s + 1] - 1)
+    return inside & (ix - 1 <= i) & (i <= ix + 2) & (lo <= k) & (k <= hi)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_integrand_gradient_vs_fd(pdf, api, torch, prec):
+    g = cfg0_grid()
+    n = 100_000
+    u1, u2 = wl.dy_uniforms(2, n)
+    vals_np = g.xf if prec == "f64" else g.xf.astype(np.float32)
+    g64 = wl.GridSpec(pids=g.pids, x=g.x, q2=g.q2, q_off=g.q_off,
+                      xf=np.asarray(vals_np, dtype=np.float64), as_q2=g.as_q2, as_val=g.as_val)
+    vals = torch.as_tensor(vals_np, device="cuda")
+    grad = torch.zeros_like(vals)
+    scale = 1.0 / n
+    api.dy_backward(pdf, u1, u2, grad, XMIN, S, scale, prec=prec, values=vals)
+    grad = grad.double().cpu().numpy()
+    x1, x2, q2 = kinematics(g, u1, u2)
+    rng = np.random.default_rng(11)
+    rows = {int(p): f for f, p in enumerate(g.pids)}
+    # flavours outside the luminosity (gluon) get exactly zero
+    assert np.all(grad[rows[21]] == 0.0)
+    res = []
+    h = 1e-4
+    while len(res) < 60:
+        pid = int(rng.choice([1, 2, 3, 4, 5, -1, -2, -3, -4, -5]))
+        f = rows[pid]
+        i = int(rng.integers(40, 99))
+        k = int(rng.integers(0, g.n_q))
+        xs = x1 if pid > 0 else x2
+        m = touched(g, xs, q2, i, k)
+        if not m.any():
+            assert grad[f, i, k] == 0.0
+            continue
+        gp = wl.GridSpec(pids=g.pids, x=g.x, q2=g.q2, q_off=g.q_off, xf=g64.xf.copy(),
+                         as_q2=g.as_q2, as_val=g.as_val)
+        gm = wl.GridSpec(pids=g.pids, x=g.x, q2=g.q2, q_off=g.q_off, xf=g64.xf.copy(),
+                         as_q2=g.as_q2, as_val=g.as_val)
+        gp.xf[f, i, k] += h
+        gm.xf[f, i, k] -= h
+        fd = scale * np.sum(oracle.dy(gp, u1[m], u2[m], XMIN, S) -
+                            oracle.dy(gm, u1[m], u2[m], XMIN, S)) / (2 * h)
+        res.append((grad[f, i, k], fd))
+    a = np.array(res)
+    sc = max(1e-300, 1e-2 * math.sqrt(np.mean(a[:, 1] ** 2)))
+    e = np.abs(a[:, 0] - a[:, 1]) / np.maximum(np.abs(a[:, 1]), sc)
+    print("integrand gradient %s: max metric %.2e" % (prec, e.max()))
+    assert e.max() <= 1e-6
