@@ -1,15 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the batched PDF evaluation hot path on one MI355X.
 
-One step = one pass of the whole forward path over one batch: x f for all 11
-partons at 1e7 query points (log-uniform x in [1e-6, 0.99], Q in [2, 1e4] GeV)
-on the 11 x 100 x 50 three-subgrid member grid, plus alpha_s at the same
-points.  Inputs are resident in HBM before the timed region.
+Headline step (timed K times after W warm-ups): x f for all 11 partons at 1e7
+query points (log-uniform x in [1e-6, 0.99], Q in [2, 1e4] GeV) on the
+11 x 100 x 50 three-subgrid member grid, plus alpha_s at the same points, in
+the precision given by --prec.  Inputs are resident in HBM before timing.
 
-Prints one JSON line.  `value` is points x flavours per second of the chosen
-precision (--prec f64 | f32s); the other precision, the backward pass
-(points x flavours per second of forward + backward on 1e6 points), the error
-against the oracle and the roofline of the dominant kernel ride along.
+Also measured (reported under "variants"):
+  * the other precision of the same step;
+  * forward + backward (knot and coordinate gradients) of sum w * xf on 1e6
+    points with the grid as an FP32 tensor;
+  * 101 members with uneven grids at 1e6 shared points, one launch, FP64 and
+    FP32 stencil;
+  * the fused Drell-Yan-like integrand over 1e8 points in 10 chunks of 1e7,
+    forward and knot-gradient backward, FP64 and FP32 stencil;
+  * the error against the CPU oracle on the first 1e6 points, and the oracle
+    itself timed on the host cores (cpu_baseline).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -37,11 +45,12 @@ def parse():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32s"])
     ap.add_argument("--n", type=int, default=N_PTS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="only the headline precision")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline step")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--only", default=None, choices=["xfx", "members", "dy", "bwd"],
+                    help="run one workload for a few steps (profiler runs) and print its timing")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="run a plain copy kernel of known size (for counter scaling) and exit")
-    ap.add_argument("--only", default=None, choices=[None, "xfx"],
-                    help="time only the xfx kernel (for profiler runs)")
+                    help="run a plain copy kernel of known size (counter scaling) and exit")
     return ap.parse_args()
 
 
@@ -49,23 +58,24 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def time_steps(torch, fn_step, steps, warmup, stream):
-    """W untimed steps, then exactly K timed steps bracketed by synchronize."""
-    for _ in range(warmup):
-        fn_step(None)
-    torch.cuda.synchronize()
-    ev = []
-    t0 = time.perf_counter()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(steps):
-        fn_step(ev)
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    total_ms = start.elapsed_time(end)
-    return total_ms / steps, wall, ev
+def recorded_traffic(prec, launch):
+    """HBM bytes per launch of the forward kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record, if it was taken on the same kernel source,
+    precision and launch shape; otherwise None."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "xfx_fwd_1e7x11_hbm_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in ("xfx_fwd_impl.h", "xfx_f64.hip", "xfx_f32s.hip", "pdfx_internal.h"):
+        with open(os.path.join(HERE, "paper_2012_08221_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if (rec.get("kernel_source_sha256") != h.hexdigest() or rec.get("prec") != prec
+            or list(rec.get("launch_shape", [])) != list(launch)):
+        return None
+    return float(rec["traffic_bytes"])
 
 
 def main():
@@ -75,108 +85,210 @@ def main():
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2012_08221_amd import api
+    from paper_2012_08221_amd import api, autograd as ag
     from paper_2012_08221_amd import workloads as wl
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
+    def timed(fn, reps, warm=1):
+        """Mean ms per call over `reps` calls, HIP events on the launch stream."""
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
     if args.calib_copy:
         n = 1 << 27                                   # 1 GiB of FP64 in, 1 GiB out
         a = torch.ones(n, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
-        for _ in range(5):
-            torch.mul(a, 1.0, out=b)
-        torch.cuda.synchronize()
+        ms = timed(lambda: torch.mul(a, 1.0, out=b), 5)
         print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8,
-                          "launches": 5}))
+                          "ms": ms, "gbs": 2 * n * 8 / ms / 1e6}))
         return
 
     grid = wl.config0_grid()
     pdf = api.mkPDF(grid)
-    n = args.n
-    log("generating %d query points" % n)
-    x_np, q2_np = wl.queries(1, n)
-    x = torch.as_tensor(x_np, device=dev)
-    q2 = torch.as_tensor(q2_np, device=dev)
     pids = grid.pids
     nf = len(pids)
-    torch.cuda.synchronize()
+    n = args.n
+    variants = {}
 
-    def bench_prec(prec, with_alphas=True):
-        dt = api.prec_dtype(prec)
-        out = torch.empty((n, nf), dtype=dt, device=dev)
-        aout = torch.empty(n, dtype=dt, device=dev)
+    if args.only in (None, "xfx"):
+        log("generating %d query points" % n)
+        x_np, q2_np = wl.queries(1, n)
+        x = torch.as_tensor(x_np, device=dev)
+        q2 = torch.as_tensor(q2_np, device=dev)
+        torch.cuda.synchronize()
+        if not args.no_tune:
+            for prec in ("f64", "f32s"):
+                pdf.autotune(prec, n_req=nf, n_pts=n)
+        results = {}
+        precs = [args.prec] + ([] if (args.no_extra or args.only)
+                               else [p for p in ("f64", "f32s") if p != args.prec])
+        for prec in precs:
+            dt = api.prec_dtype(prec)
+            out = torch.empty((n, nf), dtype=dt, device=dev)
+            aout = torch.empty(n, dtype=dt, device=dev)
+            ev = []
 
-        def step(ev):
-            if ev is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-            pdf.xfxQ2(pids, x, q2, prec=prec, out=out)
-            if ev is not None:
-                e1.record(stream)
-                ev.append((e0, e1))
-            if with_alphas:
-                pdf.alphasQ2(q2, prec=prec, out=aout)
+            def step(rec):
+                if rec:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                pdf.xfxQ2(pids, x, q2, prec=prec, out=out)
+                if rec:
+                    e1.record(stream)
+                    ev.append((e0, e1))
+                if args.only is None:
+                    pdf.alphasQ2(q2, prec=prec, out=aout)
 
-        ms, wall, ev = time_steps(torch, step, args.steps, args.warmup, stream)
-        k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-        return {"ms_per_step": ms, "wall_s": wall, "xfx_ms": k_ms, "out": out, "aout": aout}
+            for _ in range(args.warmup):
+                step(False)
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            for _ in range(args.steps):
+                step(True)
+            t1.record(stream)
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / args.steps
+            k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+            results[prec] = {"ms": ms, "xfx_ms": k_ms, "out": out,
+                             "launch": list(pdf.launch(prec))}
+            log("%s: %.3f ms per step, xfx kernel %.3f ms" % (prec, ms, k_ms))
+        if args.only == "xfx":
+            r = results[args.prec]
+            print(json.dumps({"only": "xfx", "prec": args.prec, "xfx_ms": r["xfx_ms"]}))
+            return
 
-    results = {}
-    precs = [args.prec] + ([] if args.no_extra else [p for p in ("f64", "f32s") if p != args.prec])
-    for prec in precs:
-        log("timing %s" % prec)
-        results[prec] = bench_prec(prec, with_alphas=args.only != "xfx")
-    if args.only == "xfx":
-        r = results[args.prec]
-        print(json.dumps({"only": "xfx", "prec": args.prec, "xfx_ms": r["xfx_ms"]}))
-        return
-
-    # Backward (loss = sum w * xf) on 1e6 points, FP32 grid as a tensor, if built.
-    fwd_bwd = None
-    try:
-        from paper_2012_08221_amd import autograd as ag
+    # forward + backward: loss = sum w * xf on 1e6 points, grid as an FP32 tensor
+    if args.only == "bwd" or (args.only is None and not args.no_extra):
         nb = 1_000_000
+        xb_np, qb_np = wl.queries(3, nb)
+        xb = torch.as_tensor(xb_np, device=dev).requires_grad_(True)
+        qb = torch.as_tensor(qb_np, device=dev).requires_grad_(True)
         vals = torch.as_tensor(grid.xf, device=dev).to(torch.float32).requires_grad_(True)
-        xb, qb = x[:nb].clone(), q2[:nb].clone()
         w = torch.as_tensor(wl.loss_weights(3, nb), device=dev).to(torch.float32)
+        pdf3 = api.mkPDF(grid, with_values=False)
 
-        def fb(ev):
-            vals.grad = None
-            y = ag.xfx(pdf, vals, pids, xb, qb)
-            (y * w).sum().backward()
-        ms_fb, _, _ = time_steps(torch, fb, max(5, args.steps // 5), 2, stream)
-        fwd_bwd = {"value": nb * nf / (ms_fb * 1e-3), "unit": "pf/s", "n_points": nb,
-                   "ms_per_step": ms_fb, "dtype": "f32s",
-                   "what": "forward + backward (grad wrt 11x100x50 knots) of sum w*xf"}
-    except (ImportError, AttributeError) as e:
-        log("backward not timed: %s" % e)
-    except Exception as e:  # noqa: BLE001
-        log("backward not timed: %s: %s" % (type(e).__name__, e))
+        def fwd():
+            return ag.xfx(pdf3, vals, pids, xb, qb, prec="f32s")
+
+        def fwd_bwd():
+            vals.grad = xb.grad = qb.grad = None
+            (fwd() * w).sum().backward()
+
+        ms_f = timed(fwd, 10, 2)
+        ms_fb = timed(fwd_bwd, 10, 2)
+        variants["fwd_bwd"] = {
+            "value": nb * nf / (ms_fb * 1e-3), "unit": "pf/s (forward+backward)",
+            "ms_per_step": ms_fb, "forward_ms": ms_f, "backward_ms": ms_fb - ms_f,
+            "n_points": nb, "dtype": "f32 stencil forward, FP64 adjoint",
+            "what": "sum w*xf, gradients w.r.t. the 11x100x50 knots, x and Q^2"}
+        log("fwd+bwd: %.3f ms (forward %.3f)" % (ms_fb, ms_f))
+        if args.only == "bwd":
+            print(json.dumps({"only": "bwd", **variants["fwd_bwd"]}))
+            return
+
+    # 101 members, one launch
+    if args.only == "members" or (args.only is None and not args.no_extra):
+        members = wl.member_grids(101)
+        pset = api.PDFSet(members)
+        nm = 1_000_000
+        xm_np, qm_np = wl.queries(2, nm)
+        xm = torch.as_tensor(xm_np, device=dev)
+        qm = torch.as_tensor(qm_np, device=dev)
+        mres = {}
+        for prec in ("f64", "f32s"):
+            if not args.no_tune:
+                pset.autotune(prec, n_req=nf, n_pts=nm)
+            outm = torch.empty((101, nm, nf), dtype=api.prec_dtype(prec), device=dev)
+            ms = timed(lambda: pset.xfxQ2(pids, xm, qm, prec=prec, out=outm), 3 if args.only else 5)
+            bpe = 8 if prec == "f64" else 4
+            mres[prec] = {"value": 101 * nm * nf / (ms * 1e-3), "unit": "pf/s", "ms": ms,
+                          "hbm_gbs_algorithmic": (101 * nm * nf * bpe + 16 * nm) / ms / 1e6}
+            del outm
+            log("members %s: %.3f ms" % (prec, ms))
+        variants["members"] = {"n_members": 101, "n_points": nm, **mres}
+        del pset
+        if args.only == "members":
+            print(json.dumps({"only": "members", **variants["members"]}))
+            return
+
+    # Drell-Yan-like integrand, 1e8 points in 10 chunks of 1e7
+    if args.only == "dy" or (args.only is None and not args.no_extra):
+        nchunk, csize = (10, 10_000_000) if not args.only else (2, 10_000_000)
+        us = []
+        for c in range(nchunk):
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(wl.SEED_BASE + 4 + c)
+            us.append((torch.rand(csize, dtype=torch.float64, device=dev, generator=gen),
+                       torch.rand(csize, dtype=torch.float64, device=dev, generator=gen)))
+        dres = {}
+        for prec in ("f64", "f32s"):
+            outd = torch.empty(csize, dtype=api.prec_dtype(prec), device=dev)
+            sums = torch.empty(4096, dtype=torch.float64, device=dev)
+            gxf = torch.zeros(grid.xf.shape, dtype=api.prec_dtype(prec), device=dev)
+            from paper_2012_08221_amd import binding as B
+
+            def fwd_all():
+                for u1, u2 in us:
+                    B.pdfx_eval_dy(pdf.handle, None, api.prec_code(prec), u1.data_ptr(),
+                                   u2.data_ptr(), csize, wl.DY_XMIN, wl.SQRT_S_DY ** 2,
+                                   outd.data_ptr(), sums.data_ptr(), stream.cuda_stream)
+
+            def bwd_all():
+                for u1, u2 in us:
+                    B.pdfx_eval_dy_backward(pdf.handle, None, api.prec_code(prec), u1.data_ptr(),
+                                            u2.data_ptr(), csize, wl.DY_XMIN, wl.SQRT_S_DY ** 2,
+                                            1.0 / (nchunk * csize), gxf.data_ptr(),
+                                            stream.cuda_stream)
+
+            ms_f = timed(fwd_all, 2)
+            ms_b = timed(bwd_all, 2)
+            npts = nchunk * csize
+            dres[prec] = {"forward_points_per_s": npts / (ms_f * 1e-3),
+                          "backward_points_per_s": npts / (ms_b * 1e-3),
+                          "forward_ms_per_chunk": ms_f / nchunk,
+                          "backward_ms_per_chunk": ms_b / nchunk}
+            log("dy %s: forward %.3f ms/chunk, backward %.3f ms/chunk" %
+                (prec, ms_f / nchunk, ms_b / nchunk))
+        variants["drell_yan"] = {"n_points": nchunk * csize, "chunk": csize, **dres}
+        if args.only == "dy":
+            print(json.dumps({"only": "dy", **variants["drell_yan"]}))
+            return
 
     head = results[args.prec]
-    value = n * nf / (head["ms_per_step"] * 1e-3)
+    value = n * nf / (head["ms"] * 1e-3)
     bytes_per_pt = 16 + nf * (8 if args.prec == "f64" else 4)
-    traffic_alg = n * bytes_per_pt
-    achieved = traffic_alg / (head["xfx_ms"] * 1e-3) / 1e9
+    achieved = n * bytes_per_pt / (head["xfx_ms"] * 1e-3) / 1e9
 
-    # CPU baseline: the oracle on the host cores, on a bounded prefix of the workload.
+    # CPU baseline: the oracle on the host cores over the workload's points,
+    # and the GPU error on its first 1e6 points
     cpu = None
     err = {}
     if not args.no_cpu:
         import oracle
-        nc = min(n, 10_000_000)
+        nc = n
         threads = oracle.default_threads()
         log("oracle on %d points, %d threads" % (nc, threads))
         t0 = time.perf_counter()
         ora = oracle.xfx(grid, pids, x_np[:nc], q2_np[:nc], nthreads=threads)
         dt = time.perf_counter() - t0
         cpu = {"value": nc * nf / dt, "unit": "pf/s", "cores": threads, "kind": "oracle",
-               "sample": "first %d of the %d points x %d flavours, FP64, %.1f s wall"
-                         % (nc, n, nf, dt)}
+               "sample": "all %d points x %d flavours of the step, FP64, %.2f s wall"
+                         % (nc, nf, dt)}
         ns = min(nc, 1_000_000)
         M = oracle.stencil_absmax(grid, pids, x_np[:ns], q2_np[:ns])
         for prec, r in results.items():
@@ -187,17 +299,15 @@ def main():
                          "per_flavour_max": [float(v) for v in e.max(axis=0)],
                          "points_checked": ns}
 
-    variants = {}
     for prec, r in results.items():
         bpp = 16 + nf * (8 if prec == "f64" else 4)
         variants[prec] = {
-            "value": n * nf / (r["ms_per_step"] * 1e-3), "unit": "pf/s",
-            "ms_per_step": r["ms_per_step"], "xfx_kernel_ms": r["xfx_ms"],
+            "value": n * nf / (r["ms"] * 1e-3), "unit": "pf/s", "ms_per_step": r["ms"],
+            "xfx_kernel_ms": r["xfx_ms"], "launch_shape": r["launch"],
             "xfx_hbm_gbs_algorithmic": n * bpp / (r["xfx_ms"] * 1e-3) / 1e9,
             "hbm_roofline_pf_s": HBM_PEAK_GBS * 1e9 / bpp * nf,
+            "lds_gather_bytes_per_pf": 16 * (8 if prec == "f64" else 4),
             **err.get(prec, {})}
-    if fwd_bwd:
-        variants["fwd_bwd"] = fwd_bwd
 
     rec = {
         "metric": METRIC,
@@ -206,7 +316,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
+        "ms_per_step": head["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -217,7 +327,8 @@ def main():
                    "n_points": n, "n_flav": nf, "grid": [nf, grid.n_x, grid.n_q],
                    "q_subgrids": [int(v) for v in np.diff(grid.q_off)], "prec": args.prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(args.prec, head["launch"]),
                      "kernel": "xfx_kernel<%s>" % ("double" if args.prec == "f64" else "float"),
                      "bytes_per_point": bytes_per_pt},
         "cpu_baseline": cpu,
