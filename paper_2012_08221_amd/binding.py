@@ -27,9 +27,12 @@ PDFX_DOMAIN_CLAMP = 1
 PDFX_MAX_REQ = 64
 
 # Launch shapes (workgroup size, points per thread) compiled into the forward
-# kernels; a negative count selects the store-as-you-go variant.
+# kernels; a negative count selects the store-as-you-go variant.  A positive
+# count holds results in registers and stages flavour groups when the
+# request allows it (else one flavour at a time).
 LAUNCH_SHAPES = ((256, 2), (256, 4), (512, 1), (512, 2), (1024, 1),
-                 (256, -2), (256, -4), (256, -8), (512, -2), (512, -4), (1024, -1), (1024, -2))
+                 (256, -2), (256, -4), (256, -8), (512, -1), (512, -2), (512, -4), (1024, -1),
+                 (1024, -2))
 
 # Every function the header declares, in header order.
 EXPORTS = (

@@ -195,7 +195,7 @@ extern "C" int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pt
     for (int i = 0; i < n_launch_shapes(); ++i) {
         const LaunchShape ls = launch_shape_at(i);
         g->shape[prec] = ls;
-        g->occ_blocks[prec] = 0;
+        g->reset_occupancy(prec);
         const double ms = time_min(
             [&](hipStream_t s) {
                 return pdfx_eval_xfx(g, nullptr, prec, pids.data(), n_req, (const double *)sc.x.ptr,
@@ -208,7 +208,7 @@ extern "C" int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pt
         }
     }
     g->shape[prec] = best_ls;
-    g->occ_blocks[prec] = 0;
+    g->reset_occupancy(prec);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess)
         return fail_hip(e, "tuning");

@@ -69,8 +69,8 @@ __global__ __launch_bounds__(BLOCK) void set_kernel(const SetArgs a)
             for (int j = 0; j < PPT; ++j) {
                 const int64_t p = p0 + (int64_t)j * BLOCK;
                 live[j] = p < a.n;
-                double xv = live[j] ? a.x[p] : md.ax.lo;
-                double qv = live[j] ? a.q[p] : md.aq.lo;
+                double xv = load_point(a.x, p, a.n);
+                double qv = load_point(a.q, p, a.n);
                 const bool nan_in = (xv != xv) || (qv != qv);
                 const bool inside = xv >= md.ax.lo && xv <= md.ax.hi && qv >= md.aq.lo &&
                                     qv <= md.aq.hi;

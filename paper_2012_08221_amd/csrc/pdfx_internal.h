@@ -26,6 +26,16 @@ struct alignas(8 * sizeof(T)) IntervalRec {
     T pl, plql, ql, qr, qrpr, pr;  // pl, pl-ql, ql, qr, qr-pr, pr
 };
 
+// Coordinate of point p read with p clamped to the last point (n >= 1): a
+// lane past the end reads a real point whose result is never stored.  The
+// load stays a global load; choosing between the array and a default value's
+// address would make it a flat load, and a pending flat load holds up every
+// LDS wait issued after it.
+__device__ __forceinline__ double load_point(const double *v, int64_t p, int64_t n)
+{
+    return v[p < n ? p : n - 1];
+}
+
 // Device view of one axis (global-memory tables).
 struct AxisDev {
     const double *knots;          // raw knots, non-decreasing (search on raw values)
@@ -41,6 +51,8 @@ struct AxisDev {
 };
 
 constexpr int kMaxReq = 64;
+// Result slots a thread of the flavour-group kernel holds in registers.
+constexpr int kGrpMaxSlots = 12;
 
 // Byte offsets of one axis' tables inside the workgroup's LDS.
 struct AxisLds {
@@ -71,6 +83,15 @@ struct XfxArgs {
     unsigned long long *dom_count;
     AxisLds lx, lq;               // table offsets in LDS
     int lds_slab0, lds_slab1;     // slab buffer offsets in LDS
+    // Flavour-group staging: grid rows gi*G .. gi*G+G-1 (G = 16 / value
+    // size, rows >= nf zero) interleaved per knot into 16-byte nodes, one
+    // bordered node slab of (nx+2) x (nq+2) nodes per group.
+    const void *gvals;            // [n_groups][gstride] nodes, node slab first, then zeros
+    int gstride;                  // nodes per group in HBM
+    int n_stage;                  // groups touched by the request
+    int sgrp[kGrpMaxSlots];       // group of stage s
+    int slot_u[kGrpMaxSlots];     // slot s*G+g -> distinct request row u, or -1
+    int out_pass_pts;             // > 0: output rows staged in LDS this many points at a time
 };
 
 struct BwdArgs {
@@ -175,6 +196,30 @@ hipError_t launch_xfx_f64(const XfxArgs &a, LaunchShape ls, int max_blocks, hipS
 hipError_t launch_xfx_f32s(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
 hipError_t xfx_occupancy_f64(const XfxArgs &a, LaunchShape ls, int *blocks_per_cu);
 hipError_t xfx_occupancy_f32s(const XfxArgs &a, LaunchShape ls, int *blocks_per_cu);
+hipError_t launch_xfx_grp_f64(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
+hipError_t launch_xfx_grp_f32s(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
+hipError_t xfx_grp_occupancy_f64(const XfxArgs &a, LaunchShape ls, int *blocks_per_cu);
+hipError_t xfx_grp_occupancy_f32s(const XfxArgs &a, LaunchShape ls, int *blocks_per_cu);
+// True if the grouped kernel is compiled for ls and its prefetch covers a
+// node slab of an nx x nq grid.
+bool grp_shape_supported(LaunchShape ls, int nx, int nq);
+// Nodes per flavour group in HBM: the node slab padded with zeros up to the
+// widest prefetch of the compiled grouped shapes, so prefetches need no
+// bounds test.
+int grp_slab_stride(int nx, int nq);
+// Raw caller values [nf][nx][nq] -> flavour-group node slabs [n_groups][gstride]
+// ((nx+2) x (nq+2) nodes with a zero border, or nx x nq without; zero padding
+// rows and nodes).
+hipError_t launch_grp_repack(const void *src, void *dst, int nf, int nx, int nq, int n_groups,
+                             int gstride, bool border, bool f32, hipStream_t s);
+hipError_t launch_xfx_dma_f64(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
+hipError_t launch_xfx_dma_f32s(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s);
+hipError_t xfx_dma_occupancy_f64(LaunchShape ls, int *blocks_per_cu);
+hipError_t xfx_dma_occupancy_f32s(LaunchShape ls, int *blocks_per_cu);
+// True if the double-buffered kernel is compiled for ls and its static LDS
+// holds two node slabs and the search tables of an nx x nq grid with nbx and
+// nbq bucket seeds.
+bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq);
 hipError_t launch_alphas(const AlphasArgs &a, bool f32, hipStream_t s);
 hipError_t launch_repack(const RepackArgs &a, bool f32, hipStream_t s);
 hipError_t launch_backward(const BwdArgs &a, bool f32, void *grad_xf, double *grad_x,
@@ -198,5 +243,10 @@ size_t xfx_lds_layout(XfxArgs &a, bool f32, bool *double_buffer);
 int slab_elems_for(int nx, int nq, bool f32);
 
 constexpr size_t kLdsLimit = 160 * 1024;
+
+// LDS bytes of the flavour-group kernel with workgroup size block (axis
+// tables + one node slab padded to the prefetch width), 0 if that exceeds the
+// LDS of a compute unit or no prefetch width covers the slab.
+size_t grp_lds_layout(XfxArgs &a, bool f32, int block);
 
 }  // namespace pdfx

@@ -485,6 +485,26 @@ static std::vector<V> bordered_slabs(const double *xf, int nf, int nx, int nq, i
     return out;
 }
 
+// Flavour-group node slabs: rows G at a time (G = 16 / sizeof(V)), each knot
+// of the (nx+2) x (nq+2) slab with a border one knot wide (or of the nx x nq
+// slab without) holding its G row values side by side, one group every
+// gstride nodes; rows past nf, the border and the padding are 0.
+template <typename V>
+static std::vector<V> group_slabs(const double *xf, int nf, int nx, int nq, int n_groups,
+                                  int gstride, int border)
+{
+    constexpr int G = 16 / (int)sizeof(V);
+    const int w = nq + 2 * border;          // nodes per slab row
+    const size_t nodes = (size_t)gstride;   // group stride in nodes (slab + zero padding)
+    std::vector<V> out((size_t)n_groups * nodes * G, V(0));
+    for (int f = 0; f < nf; ++f)
+        for (int i = 0; i < nx; ++i)
+            for (int k = 0; k < nq; ++k)
+                out[((size_t)(f / G) * nodes + (size_t)(i + border) * w + (k + border)) * G +
+                    f % G] = (V)xf[((size_t)f * nx + i) * nq + k];
+    return out;
+}
+
 int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
 {
     g->nf = d->n_flav;
@@ -500,6 +520,11 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
     const int nx = g->ax.n, nq = g->aq.n;
     g->slab_elems[PDFX_F64] = slab_elems_for(nx, nq, false);
     g->slab_elems[PDFX_F32S] = slab_elems_for(nx, nq, true);
+    g->n_groups[PDFX_F64] = (g->nf + 1) / 2;
+    g->n_groups[PDFX_F32S] = (g->nf + 3) / 4;
+    g->gstride = grp_slab_stride(nx, nq);
+    g->dma_grid = dma_supported(LaunchShape{512, 1}, nx, nq, g->ax.nbuckets, g->aq.nbuckets);
+    const size_t node_bytes = (size_t)g->gstride * 16;
     hipError_t e;
     if (d->xf) {
         auto v64 = bordered_slabs<double>(d->xf, g->nf, nx, nq, g->slab_elems[PDFX_F64]);
@@ -508,12 +533,31 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
             return fail_hip(e, "upload values");
         if ((e = g->vals[PDFX_F32S].upload(v32.data(), v32.size() * sizeof(float))) != hipSuccess)
             return fail_hip(e, "upload values");
+        auto g64 = group_slabs<double>(d->xf, g->nf, nx, nq, g->n_groups[PDFX_F64], g->gstride, 1);
+        auto g32 = group_slabs<float>(d->xf, g->nf, nx, nq, g->n_groups[PDFX_F32S], g->gstride, 1);
+        if ((e = g->gvals[PDFX_F64].upload(g64.data(), g64.size() * sizeof(double))) != hipSuccess)
+            return fail_hip(e, "upload values");
+        if ((e = g->gvals[PDFX_F32S].upload(g32.data(), g32.size() * sizeof(float))) != hipSuccess)
+            return fail_hip(e, "upload values");
+        if (g->dma_grid) {
+            auto d64 = group_slabs<double>(d->xf, g->nf, nx, nq, g->n_groups[PDFX_F64], nx * nq, 0);
+            auto d32 = group_slabs<float>(d->xf, g->nf, nx, nq, g->n_groups[PDFX_F32S], nx * nq, 0);
+            if ((e = g->dvals[PDFX_F64].upload(d64.data(), d64.size() * sizeof(double))) != hipSuccess)
+                return fail_hip(e, "upload values");
+            if ((e = g->dvals[PDFX_F32S].upload(d32.data(), d32.size() * sizeof(float))) != hipSuccess)
+                return fail_hip(e, "upload values");
+        }
         g->has_values = true;
     }
-    // bordered copies of caller-provided values land here
+    // repacked copies of caller-provided values land here
     for (int p = 0; p < 2; ++p) {
         const size_t bytes = (size_t)g->nf * g->slab_elems[p] * (p == PDFX_F64 ? 8 : 4);
         if ((e = g->scratch_vals[p].upload(nullptr, bytes)) != hipSuccess)
+            return fail_hip(e, "allocate value scratch");
+        if ((e = g->scratch_gvals[p].upload(nullptr, g->n_groups[p] * node_bytes)) != hipSuccess)
+            return fail_hip(e, "allocate value scratch");
+        if (g->dma_grid && (e = g->scratch_dvals[p].upload(nullptr, (size_t)g->n_groups[p] * nx *
+                                                                        nq * 16)) != hipSuccess)
             return fail_hip(e, "allocate value scratch");
     }
     if (d->n_as > 0) {
@@ -624,19 +668,83 @@ int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int
     return PDFX_OK;
 }
 
-// Repack caller values (if any) and launch the forward kernel.
+// Stages of the flavour-group kernel for the request in a: the groups holding
+// its distinct rows, in order of first use, and where each result slot goes.
+// False if more groups are touched than the kernel holds results for.
+static bool plan_stages(XfxArgs &a, int G)
+{
+    a.n_stage = 0;
+    for (int k = 0; k < kGrpMaxSlots; ++k)
+        a.slot_u[k] = -1;
+    for (int u = 0; u < a.n_u; ++u) {
+        const int gi = a.urow[u] / G;
+        int st = 0;
+        while (st < a.n_stage && a.sgrp[st] != gi)
+            ++st;
+        if (st == a.n_stage) {
+            if ((a.n_stage + 1) * G > kGrpMaxSlots)
+                return false;
+            a.sgrp[a.n_stage++] = gi;
+        }
+        a.slot_u[st * G + a.urow[u] % G] = u;
+    }
+    return true;
+}
+
+// Repack caller values (if any) and launch the forward kernel.  Shapes with
+// results held in registers (ppt > 0) use the flavour-group kernels when the
+// request's groups fit them: the double-buffered one when the grid fits its
+// LDS and `out` is 16-byte aligned, else the single-buffer one when its slab
+// fits; everything else uses the per-flavour kernel.
 int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s)
 {
     hipError_t e;
     const bool f32 = prec == PDFX_F32S;
+    const LaunchShape ls = g->shape[prec];
+    const bool staged = ls.ppt > 0 && plan_stages(a, f32 ? 4 : 2);
+    if (staged && g->dma_grid && (uintptr_t)a.out % 16 == 0 &&
+        dma_supported(ls, a.nx, a.nq, a.ax.nbuckets, a.aq.nbuckets)) {
+        a.gvals = g->dvals[prec].ptr;
+        a.gstride = a.nx * a.nq;
+        if (xf_dev) {
+            if ((e = launch_grp_repack(xf_dev, g->scratch_dvals[prec].ptr, g->nf, a.nx, a.nq,
+                                       g->n_groups[prec], a.gstride, false, f32, s)) != hipSuccess)
+                return fail_hip(e, "repack launch");
+            a.gvals = g->scratch_dvals[prec].ptr;
+        }
+        const int maxb = g->max_blocks(prec, a, 2);
+        e = f32 ? launch_xfx_dma_f32s(a, ls, maxb, s) : launch_xfx_dma_f64(a, ls, maxb, s);
+        if (e != hipSuccess)
+            return fail_hip(e, "xfx launch");
+        return PDFX_OK;
+    }
+    bool grouped = staged && grp_shape_supported(ls, a.nx, a.nq);
+    if (grouped) {
+        XfxArgs probe = a;
+        grouped = grp_lds_layout(probe, f32, ls.block) != 0;
+    }
+    if (grouped) {
+        a.gvals = g->gvals[prec].ptr;
+        a.gstride = g->gstride;
+        if (xf_dev) {
+            if ((e = launch_grp_repack(xf_dev, g->scratch_gvals[prec].ptr, g->nf, a.nx, a.nq,
+                                       g->n_groups[prec], g->gstride, true, f32, s)) != hipSuccess)
+                return fail_hip(e, "repack launch");
+            a.gvals = g->scratch_gvals[prec].ptr;
+        }
+        const int maxb = g->max_blocks(prec, a, 1);
+        e = f32 ? launch_xfx_grp_f32s(a, ls, maxb, s) : launch_xfx_grp_f64(a, ls, maxb, s);
+        if (e != hipSuccess)
+            return fail_hip(e, "xfx launch");
+        return PDFX_OK;
+    }
     if (xf_dev) {
         RepackArgs r{xf_dev, g->scratch_vals[prec].ptr, g->nf, a.nx, a.nq, a.slab_elems};
         if ((e = launch_repack(r, f32, s)) != hipSuccess)
             return fail_hip(e, "repack launch");
         a.vals = g->scratch_vals[prec].ptr;
     }
-    const LaunchShape ls = g->shape[prec];
-    const int maxb = g->max_blocks(prec, a);
+    const int maxb = g->max_blocks(prec, a, 0);
     e = f32 ? launch_xfx_f32s(a, ls, maxb, s) : launch_xfx_f64(a, ls, maxb, s);
     if (e != hipSuccess)
         return fail_hip(e, "xfx launch");
@@ -646,20 +754,29 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
 }  // namespace pdfx
 
 // Resident workgroups of the current launch shape over the whole device
-// (cached per precision; the persistent kernel never launches more).
-int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a) const
+// (cached per precision and kernel; the persistent kernels never launch more).
+int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a, int kernel) const
 {
     const pdfx::LaunchShape ls = shape[prec];
-    if (occ_shape[prec].block == ls.block && occ_shape[prec].ppt == ls.ppt && occ_blocks[prec] > 0)
-        return occ_blocks[prec];
+    if (occ_shape[prec][kernel].block == ls.block && occ_shape[prec][kernel].ppt == ls.ppt &&
+        occ_blocks[prec][kernel] > 0)
+        return occ_blocks[prec][kernel];
     int per_cu = 0;
-    hipError_t e = prec == PDFX_F32S ? pdfx::xfx_occupancy_f32s(a, ls, &per_cu)
-                                     : pdfx::xfx_occupancy_f64(a, ls, &per_cu);
+    hipError_t e;
+    if (kernel == 2)
+        e = prec == PDFX_F32S ? pdfx::xfx_dma_occupancy_f32s(ls, &per_cu)
+                              : pdfx::xfx_dma_occupancy_f64(ls, &per_cu);
+    else if (kernel == 1)
+        e = prec == PDFX_F32S ? pdfx::xfx_grp_occupancy_f32s(a, ls, &per_cu)
+                              : pdfx::xfx_grp_occupancy_f64(a, ls, &per_cu);
+    else
+        e = prec == PDFX_F32S ? pdfx::xfx_occupancy_f32s(a, ls, &per_cu)
+                              : pdfx::xfx_occupancy_f64(a, ls, &per_cu);
     if (e != hipSuccess || per_cu < 1)
         per_cu = 1;
-    occ_shape[prec] = ls;
-    occ_blocks[prec] = per_cu * cus;
-    return occ_blocks[prec];
+    occ_shape[prec][kernel] = ls;
+    occ_blocks[prec][kernel] = per_cu * cus;
+    return occ_blocks[prec][kernel];
 }
 
 // ---------------------------------------------------------------------------

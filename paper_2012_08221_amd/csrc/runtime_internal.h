@@ -60,14 +60,23 @@ struct pdfx_grid {
     int slab_elems[2] = {0, 0};              // per precision
     pdfx::DeviceBuf vals[2];                 // owned values, bordered slabs, per precision
     pdfx::DeviceBuf scratch_vals[2];         // bordered copy of caller values, per precision
+    int n_groups[2] = {0, 0};                // flavour groups per precision (G = 2 / 4 rows)
+    int gstride = 0;                         // nodes per group slab in HBM (padded)
+    bool dma_grid = false;                   // fits the double-buffered kernel's LDS
+    pdfx::DeviceBuf dvals[2];                // owned values as borderless group slabs
+    pdfx::DeviceBuf scratch_dvals[2];        // caller values as borderless group slabs
+    pdfx::DeviceBuf gvals[2];                // owned values as flavour-group node slabs
+    pdfx::DeviceBuf scratch_gvals[2];        // caller values as flavour-group node slabs
     pdfx::DeviceBuf as_vals64, as_vals32;    // padded [n_as + 2]
     pdfx::DeviceBuf dom_count;               // unsigned long long
     pdfx::LaunchShape shape[2];              // per precision
     mutable pdfx::DeviceBuf bwd_ws;          // adjoint workspace (grows on demand)
-    mutable pdfx::LaunchShape occ_shape[2] = {{0, 0}, {0, 0}};
-    mutable int occ_blocks[2] = {0, 0};
+    // resident-workgroup cache per [precision][kernel: per-flavour, grouped, double-buffered]
+    mutable pdfx::LaunchShape occ_shape[2][3] = {};
+    mutable int occ_blocks[2][3] = {};
     int row_of(int pid) const;
-    int max_blocks(int prec, const pdfx::XfxArgs &a) const;
+    int max_blocks(int prec, const pdfx::XfxArgs &a, int kernel) const;
+    void reset_occupancy(int prec) const { occ_blocks[prec][0] = occ_blocks[prec][1] = occ_blocks[prec][2] = 0; }
 };
 
 namespace pdfx {

@@ -1,0 +1,27 @@
+// FP64 instances of the double-buffered flavour-group forward kernel.
+#include "xfx_dma_impl.h"
+
+namespace pdfx {
+
+hipError_t launch_xfx_dma_f64(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s)
+{
+    return fwd::launch_dma_typed<double>(a, ls, max_blocks, s);
+}
+
+hipError_t xfx_dma_occupancy_f64(LaunchShape ls, int *blocks_per_cu)
+{
+    return fwd::dma_occupancy_typed<double>(ls, blocks_per_cu);
+}
+
+bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq)
+{
+    if (nx < 4 || nq < 4 || nx * nq > fwd::kDmaNodes || nx + nq > fwd::kDmaKnots ||
+        nbx + nbq > fwd::kDmaSeeds)
+        return false;
+    for (const auto &k : fwd::kDmaShapes)
+        if (k.block == ls.block && k.ppt == ls.ppt)
+            return true;
+    return false;
+}
+
+}  // namespace pdfx

@@ -206,8 +206,8 @@ __global__ __launch_bounds__(BLOCK) void xfx_kernel(const XfxArgs a)
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int64_t p = (int64_t)blockIdx.x * tile_pts + tid + (int64_t)j * BLOCK;
-        xnext[j] = p < a.n ? a.x[p] : a.ax.lo;
-        qnext[j] = p < a.n ? a.q[p] : a.aq.lo;
+        xnext[j] = a.n > 0 ? load_point(a.x, p, a.n) : a.ax.lo;
+        qnext[j] = a.n > 0 ? load_point(a.q, p, a.n) : a.aq.lo;
     }
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -221,8 +221,8 @@ __global__ __launch_bounds__(BLOCK) void xfx_kernel(const XfxArgs a)
             xcur[j] = xnext[j];
             qcur[j] = qnext[j];
             const int64_t pn = p0 + (int64_t)gridDim.x * tile_pts + (int64_t)j * BLOCK;
-            xnext[j] = pn < a.n ? a.x[pn] : a.ax.lo;
-            qnext[j] = pn < a.n ? a.q[pn] : a.aq.lo;
+            xnext[j] = load_point(a.x, pn, a.n);
+            qnext[j] = load_point(a.q, pn, a.n);
         }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
@@ -324,9 +324,11 @@ __global__ __launch_bounds__(BLOCK) void xfx_kernel(const XfxArgs a)
 
 // Compiled launch shapes (block, points per thread).
 // ppt < 0 selects the store-as-you-go kernels (see with_variant).
+// Every register-result shape has a store-as-you-go twin (requests with more
+// than kRegCols distinct flavours switch to it).
 constexpr LaunchShape kShapes[] = {{256, 2}, {256, 4}, {512, 1}, {512, 2}, {1024, 1},
-                                   {256, -2}, {256, -4}, {256, -8}, {512, -2}, {512, -4},
-                                   {1024, -1}, {1024, -2}};
+                                   {256, -2}, {256, -4}, {256, -8}, {512, -1}, {512, -2},
+                                   {512, -4}, {1024, -1}, {1024, -2}};
 // Distinct flavours whose results a thread holds in registers.
 constexpr int kRegCols = 12;
 
@@ -370,6 +372,7 @@ hipError_t with_variant(const XfxArgs &a, LaunchShape ls, bool db, Call call)
     if (ls.block == 256 && ls.ppt == -2) PDFX_FWD_PF(V, 256, 2, 0);
     if (ls.block == 256 && ls.ppt == -4) PDFX_FWD_PF(V, 256, 4, 0);
     if (ls.block == 256 && ls.ppt == -8) PDFX_FWD_PF(V, 256, 8, 0);
+    if (ls.block == 512 && ls.ppt == -1) PDFX_FWD_PF(V, 512, 1, 0);
     if (ls.block == 512 && ls.ppt == -2) PDFX_FWD_PF(V, 512, 2, 0);
     if (ls.block == 512 && ls.ppt == -4) PDFX_FWD_PF(V, 512, 4, 0);
     if (ls.block == 1024 && ls.ppt == -1) PDFX_FWD_PF(V, 1024, 1, 0);

@@ -83,6 +83,32 @@ def test_all_launch_shapes_agree(pdf0, torch, prec):
         pdf0.set_launch(prec, *keep)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_unaligned_out_matches_aligned(pdf0, torch, api, prec):
+    """An output buffer that is not 16-byte aligned takes the flavour-group
+    kernel without LDS output staging (the double-buffered kernel needs
+    16-byte stores); every register-result shape must still agree bitwise."""
+    g = cfg0_grid()
+    x, q2 = cfg0_queries(30_001)
+    xd = torch.as_tensor(x, device="cuda")
+    qd = torch.as_tensor(q2, device="cuda")
+    n = x.shape[0]
+    keep = pdf0.launch(prec)
+    try:
+        for blk, ppt in ((256, 2), (512, 1), (512, 2), (1024, 1)):
+            pdf0.set_launch(prec, blk, ppt)
+            ref = pdf0.xfxQ2(g.pids, xd, qd, prec=prec).cpu().numpy()
+            buf = torch.full((n * 11 + 1,), -7.0, dtype=api.prec_dtype(prec), device="cuda")
+            out = buf[1:].view(n, 11)
+            assert out.data_ptr() % 16 != 0
+            pdf0.xfxQ2(g.pids, xd, qd, prec=prec, out=out)
+            np.testing.assert_array_equal(out.cpu().numpy(), ref)
+            assert buf[0].item() == -7.0
+            check(g, ref, x, q2, g.pids, prec, "shape%dx%d" % (blk, ppt))
+    finally:
+        pdf0.set_launch(prec, *keep)
+
+
 @pytest.mark.parametrize("n", [0, 1, 63, 65, 255, 1023, 1025, 4097, 12345])
 def test_ragged_sizes(pdf0, n):
     g = cfg0_grid()
@@ -223,9 +249,21 @@ def test_small_and_uneven_grids(api, nx, counts):
     # scaled by the grid's weight condition (1 on uniformly spaced grids)
     tol32 = f32_tolerance(g)
     print("grid%d f32 tolerance %.2e" % (nx, tol32))
+    import torch
     for prec in ("f64", "f32s"):
-        check(g, p.xfxQ2(pids, xq, qq, prec=prec).cpu().numpy(), xq, qq, pids, prec,
-              "grid%d" % nx, tol=None if prec == "f64" else tol32)
+        tol = None if prec == "f64" else tol32
+        # register-result shape: double-buffered kernel where the grid fits
+        # it, flavour-group or per-flavour kernel otherwise
+        ref = p.xfxQ2(pids, xq, qq, prec=prec).cpu().numpy()
+        check(g, ref, xq, qq, pids, prec, "grid%d" % nx, tol=tol)
+        # 8- / 4-byte aligned output: no LDS-staged output rows
+        buf = torch.empty(n * 3 + 1, dtype=api.prec_dtype(prec), device="cuda")
+        out = buf[1:].view(n, 3)
+        p.xfxQ2(pids, xq, qq, prec=prec, out=out)
+        np.testing.assert_array_equal(out.cpu().numpy(), ref)
+        # store-as-you-go shape: per-flavour kernel
+        p.set_launch(prec, 512, -1)
+        np.testing.assert_array_equal(p.xfxQ2(pids, xq, qq, prec=prec).cpu().numpy(), ref)
 
 
 def test_caller_values_match_owned(pdf0, torch):
