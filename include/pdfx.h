@@ -193,6 +193,13 @@ int pdfx_get_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
 /* Forces a launch shape (must be one of the compiled ones). */
 int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 
+/* Launch shape of the double-buffered integrand kernel (pdfx_eval_dy on
+ * grids with the 11 partons in the standard order that fit its LDS):
+ * workgroup size and points per thread; compiled: (512, 1), (512, 2),
+ * (256, 2).  Other grids use a fixed single-slab kernel. */
+int pdfx_get_dy_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
+int pdfx_set_dy_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
+
 /* ---- diagnostics ---- */
 
 /* Number of out-of-grid points counted since the last call, over all eval

@@ -120,6 +120,12 @@ class PDF:
     def set_launch(self, prec, block, ppt):
         B.pdfx_set_launch(self.handle, prec_code(prec), block, ppt)
 
+    def dy_launch(self, prec="f64"):
+        return B.pdfx_get_dy_launch(self.handle, prec_code(prec))
+
+    def set_dy_launch(self, prec, block, ppt):
+        B.pdfx_set_dy_launch(self.handle, prec_code(prec), block, ppt)
+
     def autotune(self, prec="f64", n_req=None, n_pts=1 << 22, cache_path=None):
         B.pdfx_autotune(self.handle, prec_code(prec), n_req or self.n_flav, n_pts, cache_path)
         return self.launch(prec)

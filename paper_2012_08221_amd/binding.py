@@ -40,6 +40,7 @@ EXPORTS = (
     "pdfx_eval_alphas", "pdfx_eval_xfx_backward", "pdfx_load_set", "pdfx_free_set",
     "pdfx_eval_set_xfx", "pdfx_eval_dy", "pdfx_dy_max_blocks", "pdfx_eval_dy_backward",
     "pdfx_autotune", "pdfx_autotune_set", "pdfx_get_launch", "pdfx_set_launch",
+    "pdfx_get_dy_launch", "pdfx_set_dy_launch",
     "pdfx_domain_errors", "pdfx_last_error", "pdfx_version",
 )
 
@@ -98,6 +99,8 @@ def lib():
             "pdfx_autotune_set": ([vp, i32, i32, i64, ctypes.c_char_p], i32),
             "pdfx_get_launch": ([vp, i32, vp, vp], i32),
             "pdfx_set_launch": ([vp, i32, i32, i32], i32),
+            "pdfx_get_dy_launch": ([vp, i32, vp, vp], i32),
+            "pdfx_set_dy_launch": ([vp, i32, i32, i32], i32),
             "pdfx_domain_errors": ([vp, vp], i32),
             "pdfx_last_error": ([], ctypes.c_char_p),
             "pdfx_version": ([], ctypes.c_char_p),
@@ -236,6 +239,16 @@ def pdfx_get_launch(h, prec):
 
 def pdfx_set_launch(h, prec, block, ppt):
     return check(lib().pdfx_set_launch(h, prec, block, ppt))
+
+
+def pdfx_get_dy_launch(h, prec):
+    b, p = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().pdfx_get_dy_launch(h, prec, ctypes.byref(b), ctypes.byref(p)))
+    return b.value, p.value
+
+
+def pdfx_set_dy_launch(h, prec, block, ppt):
+    return check(lib().pdfx_set_dy_launch(h, prec, block, ppt))
 
 
 def pdfx_domain_errors(h) -> int:

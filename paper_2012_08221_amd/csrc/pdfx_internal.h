@@ -91,6 +91,10 @@ struct XfxArgs {
     int n_stage;                  // groups touched by the request
     int sgrp[kGrpMaxSlots];       // group of stage s
     int slot_u[kGrpMaxSlots];     // slot s*G+g -> distinct request row u, or -1
+    int slot_col[kGrpMaxSlots];   // slot -> first output column of its row, or -1
+    int n_dup;                    // further columns of a row requested more than once:
+    int dup_src[kMaxReq];         //   column dup_dst[d] repeats column dup_src[d]
+    int dup_dst[kMaxReq];
     int out_pass_pts;             // > 0: output rows staged in LDS this many points at a time
 };
 
@@ -167,6 +171,8 @@ struct DyArgs {
     double *gacc;                 // [nf][nx][nq] FP64
     int lds_recx, lds_recq, lds_grad;
     int chunk;
+    const void *gvals;            // borderless flavour-group node slabs (double-buffered kernel)
+    int gstride;                  // nodes per group
 };
 
 struct AlphasArgs {
@@ -228,6 +234,13 @@ hipError_t launch_set(const SetArgs &a, bool f32, LaunchShape ls, size_t lds, in
 hipError_t launch_dy_forward(const DyArgs &a, bool f32, int cus, hipStream_t s, int *n_blocks);
 hipError_t launch_dy_backward(const DyArgs &a, bool f32, void *grad_xf, int cus, hipStream_t s);
 size_t dy_lds_layout(DyArgs &a, bool f32, bool *db);
+// Double-buffered integrand kernel: fits an nx x nq grid with na alpha_s
+// knots and nbx, nbq bucket seeds (the standard 11-parton order is checked
+// by the caller).
+bool dy_dma_supported(int nx, int nq, int na, int nbx, int nbq);
+bool dy_shape_supported(LaunchShape ls);
+hipError_t launch_dy_dma_forward(const DyArgs &a, bool f32, LaunchShape ls, int cus,
+                                 hipStream_t s, int *n_blocks);
 bool set_shape_supported(LaunchShape ls);
 int n_set_shapes();
 LaunchShape set_shape_at(int i);

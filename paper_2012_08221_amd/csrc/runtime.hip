@@ -411,6 +411,32 @@ int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
     return PDFX_OK;
 }
 
+int pdfx_get_dy_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt)
+{
+    clear_error();
+    if (!g || !block || !ppt)
+        return fail(PDFX_EINVAL, "NULL argument");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    *block = g->dy_shape[prec].block;
+    *ppt = g->dy_shape[prec].ppt;
+    return PDFX_OK;
+}
+
+int pdfx_set_dy_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
+{
+    clear_error();
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    LaunchShape ls{block, ppt};
+    if (!dy_shape_supported(ls))
+        return fail(PDFX_EINVAL, "integrand launch shape (%d, %d) not compiled", block, ppt);
+    g->dy_shape[prec] = ls;
+    return PDFX_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -687,6 +713,15 @@ static bool plan_stages(XfxArgs &a, int G)
             a.sgrp[a.n_stage++] = gi;
         }
         a.slot_u[st * G + a.urow[u] % G] = u;
+    }
+    a.n_dup = 0;
+    for (int k = 0; k < kGrpMaxSlots; ++k) {
+        const int u = a.slot_u[k];
+        a.slot_col[k] = u >= 0 ? a.ucols[a.ucol_off[u]] : -1;
+        for (int c = u >= 0 ? a.ucol_off[u] + 1 : 0; u >= 0 && c < a.ucol_off[u + 1]; ++c) {
+            a.dup_src[a.n_dup] = a.slot_col[k];
+            a.dup_dst[a.n_dup++] = a.ucols[c];
+        }
     }
     return true;
 }
@@ -1031,6 +1066,19 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
 
 namespace pdfx {
 
+// True if the integrand can use the double-buffered kernel: the grid fits
+// it and holds the 11 partons in the standard order -5 .. -1, g, 1 .. 5.
+static bool dy_dma_ok(const pdfx_grid *g)
+{
+    if (!g->dma_grid || g->nf != 11 ||
+        !dy_dma_supported(g->ax.n, g->aq.n, g->aa.n, g->ax.nbuckets, g->aq.nbuckets))
+        return false;
+    for (int q = 1; q <= 5; ++q)
+        if (g->row_of(q) != 5 + q || g->row_of(-q) != 5 - q)
+            return false;
+    return true;
+}
+
 static int prepare_dy(const pdfx_grid *g, const void *xf_dev, int prec, const double *u1,
                       const double *u2, int64_t n, double xmin, double s, DyArgs *a,
                       hipStream_t stream)
@@ -1114,7 +1162,23 @@ int pdfx_eval_dy(const pdfx_grid *g, const void *xf_dev, int prec, const double 
     a.out = out;
     a.block_sums = block_sums;
     int nb = 0;
-    hipError_t e = launch_dy_forward(a, prec == PDFX_F32S, g->cus, (hipStream_t)stream, &nb);
+    hipError_t e;
+    const bool f32 = prec == PDFX_F32S;
+    if (dy_dma_ok(g)) {
+        // double-buffered kernel over the flavour groups of the grid
+        a.gvals = g->dvals[prec].ptr;
+        a.gstride = a.nx * a.nq;
+        if (xf_dev) {
+            if ((e = launch_grp_repack(xf_dev, g->scratch_dvals[prec].ptr, g->nf, a.nx, a.nq,
+                                       g->n_groups[prec], a.gstride, false, f32,
+                                       (hipStream_t)stream)) != hipSuccess)
+                return fail_hip(e, "repack launch");
+            a.gvals = g->scratch_dvals[prec].ptr;
+        }
+        e = launch_dy_dma_forward(a, f32, g->dy_shape[prec], g->cus, (hipStream_t)stream, &nb);
+    } else {
+        e = launch_dy_forward(a, f32, g->cus, (hipStream_t)stream, &nb);
+    }
     if (e != hipSuccess)
         return fail_hip(e, "integrand launch");
     if (n_blocks)

@@ -70,6 +70,7 @@ struct pdfx_grid {
     pdfx::DeviceBuf as_vals64, as_vals32;    // padded [n_as + 2]
     pdfx::DeviceBuf dom_count;               // unsigned long long
     pdfx::LaunchShape shape[2];              // per precision
+    pdfx::LaunchShape dy_shape[2] = {{512, 1}, {512, 2}};   // double-buffered integrand kernel
     mutable pdfx::DeviceBuf bwd_ws;          // adjoint workspace (grows on demand)
     // resident-workgroup cache per [precision][kernel: per-flavour, grouped, double-buffered]
     mutable pdfx::LaunchShape occ_shape[2][3] = {};

@@ -176,54 +176,64 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
     lq.ln_lo = a.aq.ln_lo;
     lq.inv_hb = a.aq.inv_hb;
 
+    // Locating a point (domain, logs, bins, weights, window) for point p
+    // from its coordinates.
+    auto locate = [&](double xv, double qv, int64_t p, V (&ox)[4], V (&oq)[4], int &ob, bool &ook) {
+        if (a.q_is_q)
+            qv = qv * qv;
+        ook = domain(a, xv, qv);
+        count_flagged(p < a.n && !ook, a.dom_count);
+        const double lnx = log(xv);
+        const double lnq = log(qv);
+        const int ix = lbin(lx, xv, lnx);
+        const int kq = lbin(lq, qv, lnq);
+        weights_gmem<V>(a.ax, ix, lnx, ox);
+        weights_gmem<V>(a.aq, kq, lnq, oq);
+        ob = window(ix, nx, ox) * nq + window(kq, nq, oq);
+    };
+
+    // Point state of the current tile, and of the next tile (located during
+    // the current tile's stencil stages, whose time goes to LDS traffic, so
+    // that the location work overlaps it: point j in stage j, or after the
+    // stages when there are fewer).  xnext holds the coordinates of the tile
+    // after that.
+    V wx[PPT][4], wq[PPT][4];
+    int base[PPT];
+    bool ok[PPT];
+    V nwx[PPT][4], nwq[PPT][4];
+    int nbase[PPT];
+    bool nok[PPT];
     double xnext[PPT], qnext[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int64_t p = (int64_t)blockIdx.x * tile_pts + tid + (int64_t)j * BLOCK;
-        xnext[j] = load_point(a.x, p, a.n);
-        qnext[j] = load_point(a.q, p, a.n);
+        locate(load_point(a.x, p, a.n), load_point(a.q, p, a.n), p, wx[j], wq[j], base[j], ok[j]);
+        const int64_t pn = p + (int64_t)gridDim.x * tile_pts;
+        xnext[j] = load_point(a.x, pn, a.n);
+        qnext[j] = load_point(a.q, pn, a.n);
     }
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t t0 = tile * tile_pts;
-        const int64_t p0 = t0 + tid;
         const bool more = tile + gridDim.x < ntiles;
-        V wx[PPT][4], wq[PPT][4];
-        int base[PPT];
-        bool ok[PPT];
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const int64_t p = p0 + (int64_t)j * BLOCK;
-            double xv = xnext[j];
-            double qv = qnext[j];
-            if (a.q_is_q)
-                qv = qv * qv;
-            ok[j] = domain(a, xv, qv);
-            count_flagged(p < a.n && !ok[j], a.dom_count);
-            const double lnx = log(xv);
-            const double lnq = log(qv);
-            const int ix = lbin(lx, xv, lnx);
-            const int kq = lbin(lq, qv, lnq);
-            weights_gmem<V>(a.ax, ix, lnx, wx[j]);
-            weights_gmem<V>(a.aq, kq, lnq, wq[j]);
-            base[j] = window(ix, nx, wx[j]) * nq + window(kq, nq, wq[j]);
-        }
+        const int64_t pnext0 = t0 + (int64_t)gridDim.x * tile_pts + tid;   // next tile, point 0
+        auto locate_next = [&](int j) {
+            const int64_t pn = pnext0 + (int64_t)j * BLOCK;
+            locate(xnext[j], qnext[j], pn, nwx[j], nwq[j], nbase[j], nok[j]);
+            const int64_t pnn = pn + (int64_t)gridDim.x * tile_pts;
+            xnext[j] = load_point(a.x, pnn, a.n);
+            qnext[j] = load_point(a.q, pnn, a.n);
+        };
 
         // the tile's first slab has landed (copies of every wave)
         wait_vm();
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const int64_t pn = p0 + (int64_t)gridDim.x * tile_pts + (int64_t)j * BLOCK;
-            xnext[j] = load_point(a.x, pn, a.n);
-            qnext[j] = load_point(a.q, pn, a.n);
-        }
 
         // Stage s reads slab (s & 1).  The copy for stage s+1 goes into the
         // other slab during stage s.  The next tile's first slab goes into
         // slab0 after the last barrier of the output phase (every barrier
         // also waits for the copies in flight), so that it lands during the
-        // output stores and the next prologue.  A lone group stays in slab0.
+        // output stores.  A lone group stays in slab0.
         V res[PPT][NSG];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -233,6 +243,8 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
                 uint4 *const nxt = (s & 1) ? slab0 : slab1;
                 if (!last)
                     dma_slab<BLOCK>(nxt, gsrc + (size_t)a.sgrp[s + 1] * a.gstride, nodes);
+                if (s < PPT)
+                    locate_next(s);
                 V tmp[PPT * G];
                 dma_stage<V, PPT>(cur, base, nq, wx, wq, ok, tmp, G);
 #pragma unroll
@@ -246,6 +258,10 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
                 }
             }
         }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+            if (j >= n_stage)
+                locate_next(j);
 
         // output rows, assembled in slab1 and written as 16-byte chunks
         __syncthreads();   // every stencil read is done
@@ -261,14 +277,13 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
                 if (lp >= 0 && lp < pn) {
                     V *r = lrow + lp * n_req;
 #pragma unroll
-                    for (int k = 0; k < NSG; ++k) {
-                        const int u = a.slot_u[k];
-                        if (k < n_stage * G && u >= 0)
-                            for (int c = a.ucol_off[u]; c < a.ucol_off[u + 1]; ++c)
-                                r[a.ucols[c]] = res[j][k];
-                    }
+                    for (int k = 0; k < NSG; ++k)
+                        if (k < n_stage * G && a.slot_col[k] >= 0)
+                            r[a.slot_col[k]] = res[j][k];
                     for (int z = 0; z < a.n_zero; ++z)
                         r[a.zcols[z]] = V(0);
+                    for (int d = 0; d < a.n_dup; ++d)
+                        r[a.dup_dst[d]] = r[a.dup_src[d]];
                 }
             }
             __syncthreads();
@@ -282,6 +297,16 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
             if (tid < (bytes & 15) / 4)
                 reinterpret_cast<uint32_t *>(dst + nch * 16)[tid] =
                     reinterpret_cast<const uint32_t *>(slab1 + nch)[tid];
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                wx[j][k] = nwx[j][k];
+                wq[j][k] = nwq[j][k];
+            }
+            base[j] = nbase[j];
+            ok[j] = nok[j];
         }
     }
     wait_vm();

@@ -209,14 +209,13 @@ __global__ __launch_bounds__(BLOCK) void xfx_grp_kernel(const XfxArgs a)
                     if (lp >= 0 && lp < pn) {
                         V *r = lrow + lp * n_req;
 #pragma unroll
-                        for (int k = 0; k < NS * G; ++k) {
-                            const int u = a.slot_u[k];
-                            if (k < n_stage * G && u >= 0)
-                                for (int c = a.ucol_off[u]; c < a.ucol_off[u + 1]; ++c)
-                                    r[a.ucols[c]] = res[j][k];
-                        }
+                        for (int k = 0; k < NS * G; ++k)
+                            if (k < n_stage * G && a.slot_col[k] >= 0)
+                                r[a.slot_col[k]] = res[j][k];
                         for (int z = 0; z < a.n_zero; ++z)
                             r[a.zcols[z]] = V(0);
+                        for (int d = 0; d < a.n_dup; ++d)
+                            r[a.dup_dst[d]] = r[a.dup_src[d]];
                     }
                 }
                 __syncthreads();

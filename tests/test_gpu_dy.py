@@ -141,3 +141,43 @@ def test_integrand_gradient_vs_fd(pdf, api, torch, prec):
     e = np.abs(a[:, 0] - a[:, 1]) / np.maximum(np.abs(a[:, 1]), sc)
     print("integrand gradient %s: max metric %.2e" % (prec, e.max()))
     assert e.max() <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_integrand_kernels_agree(pdf, api, prec):
+    """A grid whose partons are not in the standard order -5 .. -1, g, 1 .. 5
+    takes the single-slab integrand kernel; the standard grid takes the
+    double-buffered one.  Same partons and values: same per-point results."""
+    g = cfg0_grid()
+    perm = np.arange(g.pids.size)[::-1].copy()
+    gp = wl.GridSpec(pids=g.pids[perm], x=g.x, q2=g.q2, q_off=g.q_off, xf=g.xf[perm].copy(),
+                     as_q2=g.as_q2, as_val=g.as_val)
+    other = api.mkPDF(gp)
+    u1, u2 = wl.dy_uniforms(3, 200_000)
+    a, sa = pdf_dy(pdf, u1, u2, prec)
+    b, sb = pdf_dy(other, u1, u2, prec)
+    np.testing.assert_array_equal(a, b)
+    assert abs(sa.sum() - sb.sum()) <= 1e-12 * np.abs(a).sum()
+    ora = oracle.dy(g, u1, u2, XMIN, S)
+    sc = scale_of(g, u1, u2)
+    e = np.abs(b - ora) / np.maximum(np.abs(ora), 0.1 * sc)
+    assert e.max() <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_integrand_launch_shapes_agree(pdf, prec):
+    u1, u2 = wl.dy_uniforms(4, 150_001)
+    keep = pdf.dy_launch(prec)
+    ref = None
+    try:
+        for shape in ((512, 1), (512, 2), (256, 2)):
+            pdf.set_dy_launch(prec, *shape)
+            got, sums = pdf_dy(pdf, u1, u2, prec)
+            if ref is None:
+                ref = got
+            else:
+                np.testing.assert_array_equal(got, ref)
+    finally:
+        pdf.set_dy_launch(prec, *keep)
+    with pytest.raises(Exception):
+        pdf.set_dy_launch(prec, 128, 3)
