@@ -33,6 +33,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+# LDS: 128 B/clk per compute unit (a lane-consecutive ds_read_b128 stream
+# reaches 125 B/clk), 256 compute units, 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
 N_PTS = 10_000_000
 METRIC = "PDF evals/sec (points×flavours) FP32 vs FP64 at stated rel. error; fwd+bwd/s"
 
@@ -73,6 +76,21 @@ def forward_kernel_name(prec, launch):
     if ppt > 0:
         return "xfx_dma_kernel<%s, %d, %d>" % (v, block, ppt)
     return "xfx_kernel<%s, %d, %d, PF, DB, 0>" % (v, block, -ppt)
+
+
+def lds_bytes(prec, launch, n, nf, nx, nq):
+    """LDS bytes one forward launch moves (double-buffered kernel, ppt > 0):
+    stencil reads (16 nodes of 16 B per point and flavour group), global-to-
+    LDS slab copies (one slab per group and tile) and the output rows staged
+    through LDS (written, then read).  None for the per-flavour kernel."""
+    block, ppt = launch
+    if ppt <= 0:
+        return None
+    vb = 8 if prec == "f64" else 4
+    g = 16 // vb
+    stages = (nf + g - 1) // g
+    tiles = (n + block * ppt - 1) // (block * ppt)
+    return n * stages * 16 * 16 + tiles * stages * nx * nq * 16 + 2 * n * nf * vb
 
 
 def recorded_traffic(prec, launch):
@@ -337,8 +355,13 @@ def main():
             "xfx_kernel_ms": r["xfx_ms"], "launch_shape": r["launch"],
             "xfx_hbm_gbs_algorithmic": n * bpp / (r["xfx_ms"] * 1e-3) / 1e9,
             "hbm_roofline_pf_s": HBM_PEAK_GBS * 1e9 / bpp * nf,
-            "lds_gather_bytes_per_pf": 16 * (8 if prec == "f64" else 4),
             **err.get(prec, {})}
+        lb = lds_bytes(prec, r["launch"], n, nf, grid.n_x, grid.n_q)
+        if lb is not None:
+            variants[prec]["lds"] = {"bytes_per_launch": lb,
+                                     "achieved_gbs": lb / (r["xfx_ms"] * 1e-3) / 1e9,
+                                     "peak_gbs": LDS_PEAK_GBS,
+                                     "frac": lb / (r["xfx_ms"] * 1e-3) / 1e9 / LDS_PEAK_GBS}
 
     rec = {
         "metric": METRIC,
@@ -361,7 +384,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(args.prec, head["launch"]),
                      "kernel": forward_kernel_name(args.prec, head["launch"]),
-                     "bytes_per_point": bytes_per_pt},
+                     "bytes_per_point": bytes_per_pt,
+                     "lds": variants.get(args.prec, {}).get("lds")},
         "cpu_baseline": cpu,
         "variants": variants,
     }
