@@ -21,6 +21,7 @@
 //   finish: grad_xf += accumulator (in the caller's precision); grad_x,
 //           grad_q2 from the per-point accumulators with the chain rule and
 //           the domain rules.
+#include "bwd_internal.h"
 #include "xfx_fwd_impl.h"
 
 namespace pdfx {
@@ -233,6 +234,12 @@ int grid_blocks(int64_t n, int block, int cap)
 hipError_t launch_backward(const BwdArgs &a0, bool f32, void *grad_xf, double *grad_x,
                            double *grad_q2, int cus, hipStream_t s)
 {
+    return launch_backward_ex(a0, f32, grad_xf, grad_x, grad_q2, cus, s, false);
+}
+
+hipError_t launch_backward_ex(const BwdArgs &a0, bool f32, void *grad_xf, double *grad_x,
+                              double *grad_q2, int cus, hipStream_t s, bool coords_ready)
+{
     BwdArgs a = a0;
     hipError_t e;
     // state pass: x and Q^2 tables in LDS
@@ -263,30 +270,34 @@ hipError_t launch_backward(const BwdArgs &a0, bool f32, void *grad_xf, double *g
         const int64_t nv = (int64_t)a.nf * a.nx * a.nq;
         hipLaunchKernelGGL(zero_kernel, dim3(grid_blocks(nv, 256, 1024)), dim3(256), 0, s, a.gacc, nv);
     }
-    if (a.accx && a.n > 0) {
+    if (a.accx && a.n > 0 && !coords_ready) {
         hipLaunchKernelGGL(zero_kernel, dim3(grid_blocks(a.n, 256, 4 * cus)), dim3(256), 0, s, a.accx, a.n);
         hipLaunchKernelGGL(zero_kernel, dim3(grid_blocks(a.n, 256, 4 * cus)), dim3(256), 0, s, a.accw, a.n);
     }
+    // the flavour workgroups skip the coordinate sums when they are done
+    BwdArgs ka = a;
+    if (coords_ready)
+        ka.accx = ka.accw = nullptr;
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     // adjoint pass
-    if (a.n > 0 && a.n_u > 0 && (a.gacc || a.accx)) {
+    if (ka.n > 0 && ka.n_u > 0 && (ka.gacc || ka.accx)) {
         off = 0;
-        a.lds_recx = take((size_t)(a.ax.n - 1) * 64, 64);
-        a.lds_recq = take((size_t)(a.aq.n - 1) * 64, 64);
-        const size_t slab_n = (size_t)(a.nx + 2) * (a.nq + 2);
-        a.lds_grad = take(a.gacc ? slab_n * 8 : 0, 16);
-        a.lds_slab = take(a.accx ? (size_t)a.slab_elems * (f32 ? 4 : 8) : 0, 16);
+        ka.lds_recx = take((size_t)(ka.ax.n - 1) * 64, 64);
+        ka.lds_recq = take((size_t)(ka.aq.n - 1) * 64, 64);
+        const size_t slab_n = (size_t)(ka.nx + 2) * (ka.nq + 2);
+        ka.lds_grad = take(ka.gacc ? slab_n * 8 : 0, 16);
+        ka.lds_slab = take(ka.accx ? (size_t)ka.slab_elems * (f32 ? 4 : 8) : 0, 16);
         const size_t lds = off;
         if (lds > kLdsLimit)
             return hipErrorInvalidValue;
         // about 4 workgroups per compute unit over all (chunk, flavour) pairs
-        int64_t nchunk = (4LL * cus + a.n_u - 1) / a.n_u;
-        int64_t chunk = (a.n + nchunk - 1) / nchunk;
+        int64_t nchunk = (4LL * cus + ka.n_u - 1) / ka.n_u;
+        int64_t chunk = (ka.n + nchunk - 1) / nchunk;
         if (chunk < 1024)
             chunk = 1024;
-        nchunk = (a.n + chunk - 1) / chunk;
-        a.chunk = (int)chunk;
+        nchunk = (ka.n + chunk - 1) / chunk;
+        ka.chunk = (int)chunk;
         auto fn = f32 ? adjoint_kernel<float> : adjoint_kernel<double>;
         if (lds > 64 * 1024) {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
@@ -294,7 +305,7 @@ hipError_t launch_backward(const BwdArgs &a0, bool f32, void *grad_xf, double *g
             if (e != hipSuccess)
                 return e;
         }
-        hipLaunchKernelGGL(fn, dim3((unsigned)nchunk, (unsigned)a.n_u), dim3(kBwdBlock), lds, s, a);
+        hipLaunchKernelGGL(fn, dim3((unsigned)nchunk, (unsigned)ka.n_u), dim3(kBwdBlock), lds, s, ka);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }

@@ -1,0 +1,195 @@
+// Coordinate part of the adjoint of the batched evaluation: for every point,
+//   dL/dln x   = sum_r g[p][r] * sum_{i,k} dwx_i wq_k v_r[i][k] / d_x,
+//   dL/dln Q^2 = sum_r g[p][r] * sum_{i,k} wx_i dwq_k v_r[i][k] / d_q,
+// with dw the t-derivatives of the folded Hermite weights and d the interval
+// widths in ln x, ln Q^2 (Sec. 2.1's interpolant differentiated along each
+// axis).  Structured like the double-buffered forward kernel: the request's
+// flavour groups are staged two slabs deep by global-to-LDS copies, each
+// thread holds its point's weights, derivative weights and dL/dout values,
+// and the two sums are accumulated in registers and written once per point,
+// instead of one global atomic per point and flavour.  Arithmetic in FP64
+// whatever the values' precision.
+#include "bwd_internal.h"
+#include "xfx_dma_impl.h"
+
+namespace pdfx {
+
+namespace {
+
+using fwd::kDmaKnots;
+using fwd::kDmaNodes;
+using fwd::kDmaSeeds;
+
+// Weights and their t-derivatives for one interval record.
+__device__ __forceinline__ void fold_both(double t, const IntervalRec<double> &r, double w[4],
+                                          double dw[4])
+{
+    const double t2 = t * t, t3 = t2 * t;
+    const double h00 = 2.0 * t3 - 3.0 * t2 + 1.0, h10 = t3 - 2.0 * t2 + t;
+    const double h01 = -2.0 * t3 + 3.0 * t2, h11 = t3 - t2;
+    const double d00 = 6.0 * t2 - 6.0 * t, d10 = 3.0 * t2 - 4.0 * t + 1.0;
+    const double d01 = -6.0 * t2 + 6.0 * t, d11 = 3.0 * t2 - 2.0 * t;
+    w[0] = -h10 * r.pl;
+    w[1] = h00 + h10 * r.plql - h11 * r.qr;
+    w[2] = h01 + h10 * r.ql + h11 * r.qrpr;
+    w[3] = h11 * r.pr;
+    dw[0] = -d10 * r.pl;
+    dw[1] = d00 + d10 * r.plql - d11 * r.qr;
+    dw[2] = d01 + d10 * r.ql + d11 * r.qrpr;
+    dw[3] = d11 * r.pr;
+}
+
+// Window of interval i on an axis of n >= 4 knots (fwd::window), moving both
+// the weights and their derivatives.
+__device__ __forceinline__ int window2(int i, int n, double w[4], double dw[4])
+{
+    double tmp[4] = {dw[0], dw[1], dw[2], dw[3]};
+    const int st = fwd::window(i, n, w);
+    fwd::window(i, n, tmp);
+    for (int m = 0; m < 4; ++m)
+        dw[m] = tmp[m];
+    return st;
+}
+
+template <typename V, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
+{
+    constexpr int G = 16 / (int)sizeof(V);
+    constexpr int NS = kGrpMaxSlots / G;
+    constexpr int NSG = NS * G;
+    __shared__ uint4 slab0[kDmaNodes];
+    __shared__ uint4 slab1[kDmaNodes];
+    __shared__ double knots[kDmaKnots];
+    __shared__ uint16_t seeds[kDmaSeeds];
+    const XfxArgs &a = c.x;
+    const int tid = threadIdx.x;
+    const int nx = a.nx, nq = a.nq;
+    const int nodes = nx * nq;
+    const uint4 *gsrc = reinterpret_cast<const uint4 *>(a.gvals);
+    const V *gout = reinterpret_cast<const V *>(c.gout);
+    const int n_req = a.n_req;
+    const int n_stage = a.n_stage;
+    const int64_t ntiles = (a.n + BLOCK - 1) / BLOCK;
+    if ((int64_t)blockIdx.x >= ntiles)
+        return;
+
+    if (n_stage > 0)
+        fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * a.gstride, nodes);
+    fwd::copy_words<BLOCK>(reinterpret_cast<char *>(knots), a.ax.knots, nx * 8);
+    fwd::copy_words<BLOCK>(reinterpret_cast<char *>(knots + nx), a.aq.knots, nq * 8);
+    fwd::copy_words<BLOCK>(reinterpret_cast<char *>(seeds), a.ax.seed, a.ax.nbuckets * 2);
+    fwd::copy_words<BLOCK>(reinterpret_cast<char *>(seeds + a.ax.nbuckets), a.aq.seed,
+                           a.aq.nbuckets * 2);
+    __syncthreads();
+    fwd::LAxis lx, lq;
+    lx.k = knots;
+    lx.seed = seeds;
+    lx.n = nx;
+    lx.nb = a.ax.nbuckets;
+    lx.ln_lo = a.ax.ln_lo;
+    lx.inv_hb = a.ax.inv_hb;
+    lq.k = knots + nx;
+    lq.seed = seeds + a.ax.nbuckets;
+    lq.n = nq;
+    lq.nb = a.aq.nbuckets;
+    lq.ln_lo = a.aq.ln_lo;
+    lq.inv_hb = a.aq.inv_hb;
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t p = tile * BLOCK + tid;
+        const bool more = tile + gridDim.x < ntiles;
+        double xv = load_point(a.x, p, a.n);
+        double qv = load_point(a.q, p, a.n);
+        fwd::domain(a, xv, qv);   // clamped or replaced; the finish pass applies the domain rule
+        const double lnx = log(xv), lnq = log(qv);
+        const int ix = fwd::lbin(lx, xv, lnx);
+        const int kq = fwd::lbin(lq, qv, lnq);
+        const IntervalRec<double> rx = a.ax.rec64[ix];
+        const IntervalRec<double> rq = a.aq.rec64[kq];
+        double wx[4], dwx[4], wq[4], dwq[4];
+        fold_both((lnx - rx.z) * rx.inv_d, rx, wx, dwx);
+        fold_both((lnq - rq.z) * rq.inv_d, rq, wq, dwq);
+        const int base = window2(ix, nx, wx, dwx) * nq + window2(kq, nq, wq, dwq);
+        // dL/d(slot) summed over the slot's output columns
+        const int64_t pc = p < a.n ? p : a.n - 1;
+        double gs[NSG];
+#pragma unroll
+        for (int k = 0; k < NSG; ++k) {
+            gs[k] = 0.0;
+            const int u = a.slot_u[k];
+            if (k < n_stage * G && u >= 0)
+                for (int cc = a.ucol_off[u]; cc < a.ucol_off[u + 1]; ++cc)
+                    gs[k] += (double)gout[pc * n_req + a.ucols[cc]];
+        }
+
+        fwd::wait_vm();
+        __syncthreads();   // the tile's first group has landed
+        double sx = 0.0, sw = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (s < n_stage) {
+                const bool last = s + 1 == n_stage;
+                uint4 *const cur = (s & 1) ? slab1 : slab0;
+                uint4 *const nxt = (s & 1) ? slab0 : slab1;
+                if (!last)
+                    fwd::dma_slab<BLOCK>(nxt, gsrc + (size_t)a.sgrp[s + 1] * a.gstride, nodes);
+                double du[G], dw[G];
+#pragma unroll
+                for (int jx = 0; jx < 4; ++jx) {
+                    const uint4 *rowp = cur + base + jx * nq;
+                    double r[G], dr[G];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        V v[G];
+                        fwd::Node<V>::get(rowp + k, v);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            const double vv = (double)v[g];
+                            r[g] = (k == 0) ? wq[0] * vv : fma(wq[k], vv, r[g]);
+                            dr[g] = (k == 0) ? dwq[0] * vv : fma(dwq[k], vv, dr[g]);
+                        }
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        du[g] = (jx == 0) ? dwx[0] * r[g] : fma(dwx[jx], r[g], du[g]);
+                        dw[g] = (jx == 0) ? wx[0] * dr[g] : fma(wx[jx], dr[g], dw[g]);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    sx = fma(gs[s * G + g], du[g], sx);
+                    sw = fma(gs[s * G + g], dw[g], sw);
+                }
+                if (!last) {
+                    fwd::wait_vm();
+                    __syncthreads();
+                }
+            }
+        }
+        if (p < a.n) {
+            c.accx[p] = sx * rx.inv_d;
+            c.accw[p] = sw * rq.inv_d;
+        }
+        // next tile's first group into slab0 once every wave is done with it
+        __syncthreads();
+        if (n_stage > 1 && more)
+            fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * a.gstride, nodes);
+    }
+    fwd::wait_vm();
+}
+
+}  // namespace
+
+hipError_t launch_coord_grad(const CoordArgs &c, bool f32, int cus, hipStream_t s)
+{
+    constexpr int kBlock = 512;
+    const int64_t ntiles = (c.x.n + kBlock - 1) / kBlock;
+    int64_t grid = ntiles < cus ? ntiles : cus;   // one resident workgroup per compute unit
+    if (grid < 1)
+        grid = 1;
+    auto fn = f32 ? coord_grad_kernel<float, kBlock> : coord_grad_kernel<double, kBlock>;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+}  // namespace pdfx

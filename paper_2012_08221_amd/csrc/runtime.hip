@@ -12,6 +12,7 @@
 #include "../../include/pdfx.h"
 #include "pdfx_internal.h"
 #include "runtime_internal.h"
+#include "bwd_internal.h"
 
 using namespace pdfx;
 
@@ -841,7 +842,17 @@ extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, in
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     const bool want_coord = grad_x || grad_q2;
-    if (xf_dev && want_coord) {
+    // coordinate sums by the forward-style kernel when the grid and the
+    // request fit the double-buffered layout
+    CoordArgs ca{};
+    bool coord_fwd = false;
+    if (want_coord && n_pts > 0 && g->dma_grid) {
+        ca.x = fa;
+        coord_fwd = plan_stages(ca.x, prec == PDFX_F32S ? 4 : 2) &&
+                    dma_supported(LaunchShape{512, 1}, fa.nx, fa.nq, fa.ax.nbuckets,
+                                  fa.aq.nbuckets);
+    }
+    if (xf_dev && want_coord && !coord_fwd) {
         RepackArgs r{xf_dev, g->scratch_vals[prec].ptr, g->nf, fa.nx, fa.nq, fa.slab_elems};
         if ((e = launch_repack(r, prec == PDFX_F32S, s)) != hipSuccess)
             return fail_hip(e, "repack launch");
@@ -887,7 +898,23 @@ extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, in
     a.accx = want_coord ? (double *)(ws + o_ax) : nullptr;
     a.accw = want_coord ? (double *)(ws + o_aw) : nullptr;
     a.gacc = grad_xf ? (double *)(ws + o_g) : nullptr;
-    e = launch_backward(a, prec == PDFX_F32S, grad_xf, grad_x, grad_q2, g->cus, s);
+    if (coord_fwd) {
+        ca.x.gvals = g->dvals[prec].ptr;
+        ca.x.gstride = fa.nx * fa.nq;
+        if (xf_dev) {
+            if ((e = launch_grp_repack(xf_dev, g->scratch_dvals[prec].ptr, g->nf, fa.nx, fa.nq,
+                                       g->n_groups[prec], ca.x.gstride, false, prec == PDFX_F32S,
+                                       s)) != hipSuccess)
+                return fail_hip(e, "repack launch");
+            ca.x.gvals = g->scratch_dvals[prec].ptr;
+        }
+        ca.gout = grad_out;
+        ca.accx = a.accx;
+        ca.accw = a.accw;
+        if ((e = launch_coord_grad(ca, prec == PDFX_F32S, g->cus, s)) != hipSuccess)
+            return fail_hip(e, "adjoint launch");
+    }
+    e = launch_backward_ex(a, prec == PDFX_F32S, grad_xf, grad_x, grad_q2, g->cus, s, coord_fwd);
     if (e != hipSuccess)
         return fail_hip(e, "adjoint launch");
     return PDFX_OK;
