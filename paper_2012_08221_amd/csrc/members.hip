@@ -42,8 +42,9 @@ __global__ __launch_bounds__(BLOCK) void set_kernel(const SetArgs a)
         __syncthreads();
         if (item >= a.n_items)
             break;
-        const int m = item / a.items_per_member;
-        const int64_t t_first = (int64_t)(item - m * a.items_per_member) * a.tiles_per_item;
+        const int mi = item / a.items_per_member;
+        const int m = a.mem_ids ? a.mem_ids[mi] : mi;
+        const int64_t t_first = (int64_t)(item - mi * a.items_per_member) * a.tiles_per_item;
         const MemberDev md = a.mem[m];
         if (m != loaded) {
             fwd::load_axis<BLOCK>(sm, md.ax, a.lx, F32);
@@ -154,8 +155,12 @@ hipError_t launch_set_typed(const SetArgs &a, LaunchShape ls, size_t lds, int cu
         hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), lds, s, a);
         return hipGetLastError();
     };
+    if (ls.block == 256 && ls.ppt == 2)
+        return go(set_kernel<V, 256, 2>, 256);
     if (ls.block == 256 && ls.ppt == 4)
         return go(set_kernel<V, 256, 4>, 256);
+    if (ls.block == 512 && ls.ppt == 1)
+        return go(set_kernel<V, 512, 1>, 512);
     if (ls.block == 512 && ls.ppt == 2)
         return go(set_kernel<V, 512, 2>, 512);
     if (ls.block == 1024 && ls.ppt == 1)
@@ -165,7 +170,8 @@ hipError_t launch_set_typed(const SetArgs &a, LaunchShape ls, size_t lds, int cu
 
 }  // namespace
 
-constexpr LaunchShape kSetShapes[] = {{256, 4}, {512, 2}, {1024, 1}};
+// (512, 1), (512, 2), (256, 2) also have double-buffered instances (set_dma.hip).
+constexpr LaunchShape kSetShapes[] = {{256, 2}, {256, 4}, {512, 1}, {512, 2}, {1024, 1}};
 
 bool set_shape_supported(LaunchShape ls)
 {

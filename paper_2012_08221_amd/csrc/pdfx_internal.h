@@ -129,6 +129,7 @@ struct MemberDev {
 
 struct SetArgs {
     const MemberDev *mem;         // [n_mem] on the device
+    const int *mem_ids;           // members to evaluate (work-list order), or null: all
     int n_mem;
     int n_req, n_u;
     int urow[kMaxReq];

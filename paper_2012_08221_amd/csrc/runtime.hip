@@ -13,6 +13,7 @@
 #include "pdfx_internal.h"
 #include "runtime_internal.h"
 #include "bwd_internal.h"
+#include "set_internal.h"
 
 using namespace pdfx;
 
@@ -928,9 +929,87 @@ pdfx_set::~pdfx_set()
 {
     for (auto *g : members)
         delete g;
+    for (auto *b : dma_vals)
+        delete b;
 }
 
 namespace pdfx {
+
+// Borderless group slabs with G values of V per node: group gi holds rows
+// gi*G .. gi*G+G-1 (0 past n_flav), one every gstride nodes.
+template <typename V>
+static std::vector<V> group_slabs_g(const double *xf, int nf, int nx, int nq, int G, int gstride)
+{
+    const int n_groups = (nf + G - 1) / G;
+    std::vector<V> out((size_t)n_groups * gstride * G, V(0));
+    for (int f = 0; f < nf; ++f)
+        for (int i = 0; i < nx; ++i)
+            for (int k = 0; k < nq; ++k)
+                out[((size_t)(f / G) * gstride + (size_t)i * nq + k) * G + f % G] =
+                    (V)xf[((size_t)f * nx + i) * nq + k];
+    return out;
+}
+
+// Node-width classes of a set for the double-buffered set kernel: per member
+// and precision the widest node (16, 8, 4 bytes) whose slab fits, the group
+// slabs in that width, and the member lists per class.
+static int set_build_classes(pdfx_set *s, const pdfx_grid_desc *members, int n_mem)
+{
+    std::vector<SetMemberDev> md(n_mem);
+    const int widths[3] = {16, 8, 4};
+    hipError_t e;
+    for (int m = 0; m < n_mem; ++m) {
+        const pdfx_grid *g = s->members[m];
+        md[m].ax = g->ax.dev();
+        md[m].aq = g->aq.dev();
+        md[m].nx = g->ax.n;
+        md[m].nq = g->aq.n;
+        for (int p = 0; p < 2; ++p) {
+            const bool f32 = p == PDFX_F32S;
+            const int nb = set_node_bytes(g->ax.n, g->aq.n, g->ax.nbuckets, g->aq.nbuckets, f32);
+            md[m].nb[p] = nb;
+            md[m].gvals[p] = nullptr;
+            md[m].gstride[p] = 0;
+            int cls = -1;
+            for (int c = 0; c < 3; ++c)
+                if (widths[c] == nb)
+                    cls = c;
+            if (cls < 0) {
+                s->rest_ids[p].push_back(m);
+                continue;
+            }
+            const int vsize = f32 ? 4 : 8;
+            const int G = nb / vsize;
+            const int per16 = 16 / nb;   // nodes per 16 bytes
+            const int gstride = (g->ax.n * g->aq.n + per16 - 1) / per16 * per16;
+            auto *buf = new DeviceBuf();
+            s->dma_vals.push_back(buf);
+            if (f32) {
+                auto v = group_slabs_g<float>(members[m].xf, g->nf, g->ax.n, g->aq.n, G, gstride);
+                e = buf->upload(v.data(), v.size() * sizeof(float));
+            } else {
+                auto v = group_slabs_g<double>(members[m].xf, g->nf, g->ax.n, g->aq.n, G, gstride);
+                e = buf->upload(v.data(), v.size() * sizeof(double));
+            }
+            if (e != hipSuccess)
+                return fail_hip(e, "upload member values");
+            md[m].gvals[p] = buf->ptr;
+            md[m].gstride[p] = gstride;
+            s->cls_ids[p][cls].push_back(m);
+        }
+    }
+    if ((e = s->dma_mem.upload(md.data(), md.size() * sizeof(SetMemberDev))) != hipSuccess)
+        return fail_hip(e, "upload set descriptors");
+    for (int p = 0; p < 2; ++p) {
+        for (int c = 0; c < 4; ++c) {
+            const std::vector<int> &ids = c < 3 ? s->cls_ids[p][c] : s->rest_ids[p];
+            if (!ids.empty() &&
+                (e = s->ids_dev[p][c].upload(ids.data(), ids.size() * sizeof(int))) != hipSuccess)
+                return fail_hip(e, "upload set work lists");
+        }
+    }
+    return PDFX_OK;
+}
 
 // LDS layout of the set kernel for the largest member; 0 if it does not fit.
 static size_t set_lds_layout(const pdfx_set *s, bool f32, SetArgs *a)
@@ -1011,6 +1090,11 @@ int pdfx_load_set(const pdfx_grid_desc *members, int32_t n_mem, pdfx_set **out)
         delete s;
         return fail(PDFX_EINVAL, "the largest member does not fit one LDS slab");
     }
+    int rc = set_build_classes(s, members, n_mem);
+    if (rc != PDFX_OK) {
+        delete s;
+        return rc;
+    }
     hipError_t e;
     if ((e = s->mem_desc.upload(md.data(), md.size() * sizeof(MemberDev))) != hipSuccess ||
         (e = s->counter.upload(nullptr, 256)) != hipSuccess ||
@@ -1079,7 +1163,71 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
     a.tiles_per_item = (int)tpi;
     a.items_per_member = (int)ipm;
     a.n_items = (int)(a.n_mem * ipm);
-    hipError_t e = launch_set(a, prec == PDFX_F32S, ls, lds, s->cus, (hipStream_t)stream);
+    const bool f32 = prec == PDFX_F32S;
+    hipError_t e;
+    // Double-buffered classes: a launch shape they are compiled for, 16-byte
+    // aligned member blocks, and a request whose groups fit every class's
+    // result slots.  The other members (or all, otherwise) go through the
+    // single-slab kernel.
+    const int widths[3] = {16, 8, 4};
+    SetDmaArgs d[3];
+    bool dma = set_dma_shape_supported(ls) && (uintptr_t)out % 16 == 0 &&
+               (n_pts * n_req * (f32 ? 4 : 8)) % 16 == 0;
+    for (int c = 0; c < 3 && dma; ++c) {
+        if (s->cls_ids[prec][c].empty())
+            continue;
+        XfxArgs plan = fa;
+        if (!plan_stages(plan, widths[c] / (f32 ? 4 : 8))) {
+            dma = false;
+            break;
+        }
+        SetDmaArgs &da = d[c];
+        da = SetDmaArgs{};
+        da.mem = (const SetMemberDev *)s->dma_mem.ptr;
+        da.ids = (const int *)s->ids_dev[prec][c].ptr;
+        da.n_ids = (int)s->cls_ids[prec][c].size();
+        da.items_per_member = (int)ipm;
+        da.tiles_per_item = (int)tpi;
+        da.n_items = (int)(da.n_ids * ipm);
+        da.counter = a.counter;
+        da.n_req = n_req;
+        da.n_stage = plan.n_stage;
+        da.n_zero = plan.n_zero;
+        da.n_dup = plan.n_dup;
+        for (int k = 0; k < kGrpMaxSlots; ++k) {
+            da.sgrp[k] = plan.sgrp[k];
+            da.slot_col[k] = plan.slot_col[k];
+        }
+        for (int k = 0; k < kMaxReq; ++k) {
+            da.zcols[k] = plan.zcols[k];
+            da.dup_src[k] = plan.dup_src[k];
+            da.dup_dst[k] = plan.dup_dst[k];
+        }
+        da.x = x;
+        da.q = q2;
+        da.n = n_pts;
+        da.out = out;
+        da.domain_mode = domain_mode;
+        da.dom_count = a.dom_count;
+        int64_t pass = (int64_t)kSetSlabBytes / ((int64_t)n_req * (f32 ? 4 : 8)) / 16 * 16;
+        if (pass > tile_pts)
+            pass = tile_pts;
+        da.out_pass_pts = (int)pass;
+    }
+    if (dma) {
+        for (int c = 0; c < 3; ++c) {
+            if (s->cls_ids[prec][c].empty())
+                continue;
+            if ((e = launch_set_dma(d[c], f32, widths[c], ls, s->cus, (hipStream_t)stream)) !=
+                hipSuccess)
+                return fail_hip(e, "set launch");
+        }
+        if (s->rest_ids[prec].empty())
+            return PDFX_OK;
+        a.mem_ids = (const int *)s->ids_dev[prec][3].ptr;
+        a.n_items = (int)(s->rest_ids[prec].size() * ipm);
+    }
+    e = launch_set(a, f32, ls, lds, s->cus, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail_hip(e, "set launch");
     return PDFX_OK;

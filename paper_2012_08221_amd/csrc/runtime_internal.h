@@ -101,5 +101,11 @@ struct pdfx_set {
     pdfx::LaunchShape shape[2] = {{512, 2}, {512, 2}};
     int tiles_per_item[2] = {4, 4};
     int cus = 256;
+    // double-buffered classes (set_dma.hip): members by node width, per precision
+    pdfx::DeviceBuf dma_mem;                 // SetMemberDev[n_mem]
+    std::vector<pdfx::DeviceBuf *> dma_vals; // group slabs of every member and precision
+    std::vector<int> cls_ids[2][3];          // members of node width 16, 8, 4 bytes
+    std::vector<int> rest_ids[2];            // members left to the single-slab kernel
+    pdfx::DeviceBuf ids_dev[2][4];           // the lists above on the device
     ~pdfx_set();
 };

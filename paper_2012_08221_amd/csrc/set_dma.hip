@@ -1,0 +1,309 @@
+// Double-buffered evaluation of a PDF set: many members with uneven grids
+// (PDF sets are collections of members, Sec. 1), all at the same points.
+//
+// Each member's grid is stored as borderless flavour-group node slabs whose
+// node width NB (16, 8 or 4 bytes: G = NB / sizeof(value) flavours per node)
+// is the widest for which two slabs of the member fit the static LDS.  The
+// members of one node width form a class; each class is one persistent launch
+// over a work list of (member, run of point tiles) items taken from an atomic
+// cursor.  Per item the workgroup loads the member's knots and bucket seeds
+// into LDS; per tile it locates its points in the member's grid, walks the
+// request's flavour groups with the next group's slab copied into the spare
+// LDS slab by global-to-LDS loads (one barrier per stage), keeps the results
+// in registers and writes the tile's output rows, assembled in LDS, as
+// 16-byte chunks.  Members too large for any width keep the single-slab set
+// kernel (members.hip).
+#include "set_internal.h"
+#include "xfx_dma_impl.h"
+
+namespace pdfx {
+
+namespace {
+
+// G = NB / sizeof(V) values of one node from LDS.
+template <typename V, int NB>
+__device__ __forceinline__ void node_get(const char *p, V *v);
+template <>
+__device__ __forceinline__ void node_get<double, 16>(const char *p, double *v)
+{
+    const double2 d = *reinterpret_cast<const double2 *>(p);
+    v[0] = d.x;
+    v[1] = d.y;
+}
+template <>
+__device__ __forceinline__ void node_get<double, 8>(const char *p, double *v)
+{
+    v[0] = *reinterpret_cast<const double *>(p);
+}
+template <>
+__device__ __forceinline__ void node_get<float, 16>(const char *p, float *v)
+{
+    const float4 d = *reinterpret_cast<const float4 *>(p);
+    v[0] = d.x;
+    v[1] = d.y;
+    v[2] = d.z;
+    v[3] = d.w;
+}
+template <>
+__device__ __forceinline__ void node_get<float, 8>(const char *p, float *v)
+{
+    const float2 d = *reinterpret_cast<const float2 *>(p);
+    v[0] = d.x;
+    v[1] = d.y;
+}
+template <>
+__device__ __forceinline__ void node_get<float, 4>(const char *p, float *v)
+{
+    v[0] = *reinterpret_cast<const float *>(p);
+}
+
+__global__ void reset_cursor(unsigned int *c) { *c = 0u; }
+
+template <typename V, int NB, int BLOCK, int PPT>
+__global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
+{
+    constexpr int G = NB / (int)sizeof(V);
+    constexpr int NS = kGrpMaxSlots / G;
+    constexpr int NSG = NS * G;
+    constexpr bool F32 = sizeof(V) == 4;
+    __shared__ uint4 slab0[kSetSlabBytes / 16];
+    __shared__ uint4 slab1[kSetSlabBytes / 16];
+    __shared__ double knots[kSetKnots];
+    __shared__ uint16_t seeds[kSetSeeds];
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    const int prec = F32 ? 1 : 0;
+    const int n_req = a.n_req;
+    const int n_stage = a.n_stage;
+    const int64_t tile_pts = (int64_t)BLOCK * PPT;
+    const int64_t ntiles = (a.n + tile_pts - 1) / tile_pts;
+    int loaded = -1;
+    fwd::LAxis lx, lq;
+
+    for (;;) {
+        if (tid == 0)
+            s_item = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= a.n_items)
+            break;
+        const int mi = item / a.items_per_member;
+        const int m = a.ids[mi];
+        const int64_t t_first = (int64_t)(item - mi * a.items_per_member) * a.tiles_per_item;
+        const int64_t t_end = t_first + a.tiles_per_item < ntiles ? t_first + a.tiles_per_item : ntiles;
+        const SetMemberDev &md = a.mem[m];
+        const int nx = md.nx, nq = md.nq;
+        const int chunks = (nx * nq * NB + 15) / 16;   // 16-byte chunks per slab
+        const uint4 *gsrc = reinterpret_cast<const uint4 *>(md.gvals[prec]);
+        const size_t gstride = (size_t)md.gstride[prec] * NB / 16;   // chunks per group
+        if (n_stage > 0)
+            fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);
+        if (m != loaded) {
+            fwd::copy_words<BLOCK>(reinterpret_cast<char *>(knots), md.ax.knots, nx * 8);
+            fwd::copy_words<BLOCK>(reinterpret_cast<char *>(knots + nx), md.aq.knots, nq * 8);
+            fwd::copy_words<BLOCK>(reinterpret_cast<char *>(seeds), md.ax.seed, md.ax.nbuckets * 2);
+            fwd::copy_words<BLOCK>(reinterpret_cast<char *>(seeds + md.ax.nbuckets), md.aq.seed,
+                                   md.aq.nbuckets * 2);
+            lx.k = knots;
+            lx.seed = seeds;
+            lx.n = nx;
+            lx.nb = md.ax.nbuckets;
+            lx.ln_lo = md.ax.ln_lo;
+            lx.inv_hb = md.ax.inv_hb;
+            lq.k = knots + nx;
+            lq.seed = seeds + md.ax.nbuckets;
+            lq.n = nq;
+            lq.nb = md.aq.nbuckets;
+            lq.ln_lo = md.aq.ln_lo;
+            lq.inv_hb = md.aq.inv_hb;
+            loaded = m;
+            __syncthreads();
+        }
+        V *out = reinterpret_cast<V *>(a.out) + (int64_t)m * a.n * n_req;
+
+        for (int64_t tile = t_first; tile < t_end; ++tile) {
+            const int64_t t0 = tile * tile_pts;
+            const bool more = tile + 1 < t_end;
+            V wx[PPT][4], wq[PPT][4];
+            int base[PPT];
+            bool ok[PPT];
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const int64_t p = t0 + tid + (int64_t)j * BLOCK;
+                double xv = load_point(a.x, p, a.n);
+                double qv = load_point(a.q, p, a.n);
+                const bool nan_in = (xv != xv) || (qv != qv);
+                const bool inside = xv >= md.ax.lo && xv <= md.ax.hi && qv >= md.aq.lo &&
+                                    qv <= md.aq.hi;
+                ok[j] = true;
+                if (!inside) {
+                    if (a.domain_mode == 1 && !nan_in) {
+                        xv = fmin(fmax(xv, md.ax.lo), md.ax.hi);
+                        qv = fmin(fmax(qv, md.aq.lo), md.aq.hi);
+                    } else {
+                        ok[j] = false;
+                        xv = md.ax.lo;
+                        qv = md.aq.lo;
+                    }
+                }
+                fwd::count_flagged(p < a.n && !ok[j], a.dom_count);
+                const double lnx = log(xv), lnq = log(qv);
+                const int ix = fwd::lbin(lx, xv, lnx);
+                const int kq = fwd::lbin(lq, qv, lnq);
+                fwd::weights_gmem<V>(md.ax, ix, lnx, wx[j]);
+                fwd::weights_gmem<V>(md.aq, kq, lnq, wq[j]);
+                base[j] = fwd::window(ix, nx, wx[j]) * nq + fwd::window(kq, nq, wq[j]);
+            }
+
+            fwd::wait_vm();
+            __syncthreads();   // the tile's first group has landed
+
+            V res[PPT][NSG];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (s < n_stage) {
+                    const bool last = s + 1 == n_stage;
+                    const char *cur = reinterpret_cast<const char *>((s & 1) ? slab1 : slab0);
+                    uint4 *const nxt = (s & 1) ? slab0 : slab1;
+                    if (!last)
+                        fwd::dma_slab<BLOCK>(nxt, gsrc + (size_t)a.sgrp[s + 1] * gstride, chunks);
+#pragma unroll
+                    for (int j = 0; j < PPT; ++j) {
+                        V acc[G];
+#pragma unroll
+                        for (int jx = 0; jx < 4; ++jx) {
+                            const char *rowp = cur + (size_t)(base[j] + jx * nq) * NB;
+                            V r[G];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                V v[G];
+                                node_get<V, NB>(rowp + k * NB, v);
+#pragma unroll
+                                for (int g = 0; g < G; ++g)
+                                    r[g] = (k == 0) ? wq[j][0] * v[g] : fma(wq[j][k], v[g], r[g]);
+                            }
+#pragma unroll
+                            for (int g = 0; g < G; ++g)
+                                acc[g] = (jx == 0) ? wx[j][0] * r[g] : fma(wx[j][jx], r[g], acc[g]);
+                        }
+#pragma unroll
+                        for (int g = 0; g < G; ++g)
+                            res[j][s * G + g] = ok[j] ? acc[g] : fwd::quiet_nan<V>();
+                    }
+                    if (!last) {
+                        fwd::wait_vm();
+                        __syncthreads();
+                    }
+                }
+            }
+
+            // output rows, assembled in slab1 and written as 16-byte chunks
+            __syncthreads();   // every stencil read is done
+            const int valid = (int)(a.n - t0 < tile_pts ? a.n - t0 : tile_pts);
+            V *lrow = reinterpret_cast<V *>(slab1);
+            for (int pa = 0; pa < valid; pa += a.out_pass_pts) {
+                const int pn = valid - pa < a.out_pass_pts ? valid - pa : a.out_pass_pts;
+                if (pa > 0)
+                    __syncthreads();   // the previous pass has left LDS
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    const int lp = tid + j * BLOCK - pa;
+                    if (lp >= 0 && lp < pn) {
+                        V *r = lrow + lp * n_req;
+#pragma unroll
+                        for (int k = 0; k < NSG; ++k)
+                            if (k < n_stage * G && a.slot_col[k] >= 0)
+                                r[a.slot_col[k]] = res[j][k];
+                        for (int z = 0; z < a.n_zero; ++z)
+                            r[a.zcols[z]] = V(0);
+                        for (int d = 0; d < a.n_dup; ++d)
+                            r[a.dup_dst[d]] = r[a.dup_src[d]];
+                    }
+                }
+                __syncthreads();
+                if (pa + a.out_pass_pts >= valid && n_stage > 1 && more)
+                    fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);
+                const int bytes = pn * n_req * (int)sizeof(V);
+                char *dst = reinterpret_cast<char *>(out + (t0 + pa) * n_req);   // 16-byte aligned
+                const int nch = bytes >> 4;
+                for (int c = tid; c < nch; c += BLOCK)
+                    *reinterpret_cast<uint4 *>(dst + c * 16) = slab1[c];
+                if (tid < (bytes & 15) / 4)
+                    reinterpret_cast<uint32_t *>(dst + nch * 16)[tid] =
+                        reinterpret_cast<const uint32_t *>(slab1 + nch)[tid];
+            }
+        }
+    }
+}
+
+constexpr LaunchShape kSetDmaShapes[] = {{512, 1}, {512, 2}, {256, 2}};
+
+template <typename V, int NB>
+hipError_t launch_typed(const SetDmaArgs &a, LaunchShape ls, int cus, hipStream_t s)
+{
+    auto go = [&](auto fn, int block) -> hipError_t {
+        int64_t grid = cus;   // one resident workgroup per compute unit (LDS)
+        if (grid > a.n_items)
+            grid = a.n_items;
+        if (grid < 1)
+            grid = 1;
+        hipLaunchKernelGGL(reset_cursor, dim3(1), dim3(1), 0, s, a.counter);
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), 0, s, a);
+        return hipGetLastError();
+    };
+    if (ls.block == 512 && ls.ppt == 1)
+        return go(set_dma_kernel<V, NB, 512, 1>, 512);
+    if (ls.block == 512 && ls.ppt == 2)
+        return go(set_dma_kernel<V, NB, 512, 2>, 512);
+    if (ls.block == 256 && ls.ppt == 2)
+        return go(set_dma_kernel<V, NB, 256, 2>, 256);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int set_node_bytes(int nx, int nq, int nbx, int nbq, bool f32)
+{
+    if (nx < 4 || nq < 4 || nx + nq > kSetKnots || nbx + nbq > kSetSeeds)
+        return 0;
+    const int widths64[] = {16, 8};
+    const int widths32[] = {16, 8, 4};
+    const int *w = f32 ? widths32 : widths64;
+    const int nw = f32 ? 3 : 2;
+    for (int i = 0; i < nw; ++i) {
+        const int bytes = (nx * nq * w[i] + 15) / 16 * 16;
+        if (bytes <= kSetSlabBytes)
+            return w[i];
+    }
+    return 0;
+}
+
+bool set_dma_shape_supported(LaunchShape ls)
+{
+    for (const auto &k : kSetDmaShapes)
+        if (k.block == ls.block && k.ppt == ls.ppt)
+            return true;
+    return false;
+}
+
+hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, LaunchShape ls, int cus,
+                          hipStream_t s)
+{
+    if (f32) {
+        if (nb == 16)
+            return launch_typed<float, 16>(a, ls, cus, s);
+        if (nb == 8)
+            return launch_typed<float, 8>(a, ls, cus, s);
+        if (nb == 4)
+            return launch_typed<float, 4>(a, ls, cus, s);
+    } else {
+        if (nb == 16)
+            return launch_typed<double, 16>(a, ls, cus, s);
+        if (nb == 8)
+            return launch_typed<double, 8>(a, ls, cus, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pdfx

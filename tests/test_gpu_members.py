@@ -69,8 +69,9 @@ def test_few_members_full_points_sampled(pset, members, torch, prec):
 
 
 def test_shapes_and_work_split_agree(pset, members, tmp_path):
-    """Every compiled set shape and several work splits give the same result:
-    each (shape, tiles per item) is forced through a tuning-cache entry."""
+    """Every compiled set shape and several work splits give the same result,
+    whichever kernel evaluates a member: each (shape, tiles per item) is forced
+    through a tuning-cache entry."""
     from paper_2012_08221_amd import binding as B
     x, q2 = wl.queries(9, 30_001)
     ref = None
@@ -78,7 +79,9 @@ def test_shapes_and_work_split_agree(pset, members, tmp_path):
     pset.autotune("f64", n_req=3, n_pts=30_001, cache_path=str(cache))
     key_line = cache.read_text().strip().splitlines()[-1]
     key = key_line.split('"key": "')[1].split('"')[0]
-    for blk, ppt in ((256, 4), (512, 2), (1024, 1)):
+    # (512, 1), (512, 2), (256, 2) take the double-buffered class kernels for
+    # the members that fit them; the others the single-slab kernel
+    for blk, ppt in ((256, 4), (512, 2), (1024, 1), (512, 1), (256, 2)):
         for tpi in (1, 3):
             with open(cache, "a") as fh:
                 fh.write('{"key": "%s", "block": %d, "ppt": %d, "tpi": %d, "ms": 0}\n'
