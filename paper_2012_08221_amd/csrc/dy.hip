@@ -422,6 +422,13 @@ hipError_t launch_dy_forward(const DyArgs &a0, bool f32, int cus, hipStream_t s,
 
 hipError_t launch_dy_backward(const DyArgs &a0, bool f32, void *grad_xf, int cus, hipStream_t s)
 {
+    return launch_dy_backward_ex(a0, f32, grad_xf, cus, s, false);
+}
+
+// pairs: the knot-gradient pass by quark-antiquark pairs (dy_dma.hip)
+hipError_t launch_dy_backward_ex(const DyArgs &a0, bool f32, void *grad_xf, int cus,
+                                 hipStream_t s, bool pairs)
+{
     DyArgs a = a0;
     hipError_t e;
     size_t off = 0;
@@ -450,7 +457,10 @@ hipError_t launch_dy_backward(const DyArgs &a0, bool f32, void *grad_xf, int cus
     hipLaunchKernelGGL(dy_zero, dim3(blocks_for(nv, 1024)), dim3(256), 0, s, a.gacc, nv);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
-    if (a.n > 0 && a.n_seq > 0) {
+    if (a.n > 0 && a.n_seq > 0 && pairs) {
+        if ((e = launch_dy_pair_adjoint(a, f32, cus, s)) != hipSuccess)
+            return e;
+    } else if (a.n > 0 && a.n_seq > 0) {
         off = 0;
         a.lds_recx = take((size_t)(a.ax.n - 1) * 64, 64);
         a.lds_recq = take((size_t)(a.aq.n - 1) * 64, 64);

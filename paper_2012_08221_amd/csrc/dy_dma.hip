@@ -292,7 +292,111 @@ hipError_t dy_dma_typed(const DyArgs &a, LaunchShape ls, int cus, hipStream_t s,
     return hipErrorInvalidValue;
 }
 
+// ---- backward, one quark-antiquark pair per workgroup ----
+//
+// dI/dv_q[i][k]  = L^2 alpha_s xf_-q(x2) w1_i wq_k and
+// dI/dv_-q[i][k] = L^2 alpha_s xf_q(x1)  w2_i wq_k, summed over the points.
+// A workgroup takes one pair (q, -q) and one chunk of points: both value
+// slabs and both FP64 gradient slabs (borderless) sit in LDS, so each point's
+// state (bins, local coordinates, alpha_s from the state pass) is read and its
+// weights folded once for the two flavours, and each partner value comes from
+// a 16-tap stencil of the other flavour's slab.  The LDS gradients are added
+// to the FP64 accumulator at the end.
+
+constexpr int kPairBlock = 1024;
+
+template <typename V>
+__global__ __launch_bounds__(kPairBlock) void dy_pair_adjoint_kernel(const DyArgs a)
+{
+    constexpr int G = 16 / (int)sizeof(V);
+    __shared__ V vq[kDmaNodes];
+    __shared__ V vqb[kDmaNodes];
+    __shared__ double gq[kDmaNodes];
+    __shared__ double gqb[kDmaNodes];
+    const int q = blockIdx.y + 1;          // quark q: row 5 + q; antiquark: row 5 - q
+    const int rq = 5 + q, rqb = 5 - q;
+    const int nx = a.nx, nq = a.nq, nodes = nx * nq;
+    const V *src = reinterpret_cast<const V *>(a.gvals);
+    for (int e = threadIdx.x; e < nodes; e += kPairBlock) {
+        vq[e] = src[((size_t)(rq / G) * a.gstride + e) * G + rq % G];
+        vqb[e] = src[((size_t)(rqb / G) * a.gstride + e) * G + rqb % G];
+        gq[e] = 0.0;
+        gqb[e] = 0.0;
+    }
+    __syncthreads();
+    const int64_t p_begin = (int64_t)blockIdx.x * a.chunk;
+    const int64_t p_end = p_begin + a.chunk < a.n ? p_begin + a.chunk : a.n;
+    for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kPairBlock) {
+        const int idx1 = a.st_i1[p];
+        if (idx1 < 0)
+            continue;
+        const int i1 = idx1 & 0xffff, kq = idx1 >> 16, i2 = a.st_i2[p];
+        double w1[4], w2[4], wq[4];
+        {
+            const IntervalRec<double> r1 = a.ax.rec64[i1];
+            const IntervalRec<double> r2 = a.ax.rec64[i2];
+            const IntervalRec<double> rr = a.aq.rec64[kq];
+            fwd::fold<double>(a.st_t1[p], r1.pl, r1.plql, r1.ql, r1.qr, r1.qrpr, r1.pr, w1);
+            fwd::fold<double>(a.st_t2[p], r2.pl, r2.plql, r2.ql, r2.qr, r2.qrpr, r2.pr, w2);
+            fwd::fold<double>(a.st_tq[p], rr.pl, rr.plql, rr.ql, rr.qr, rr.qrpr, rr.pr, wq);
+        }
+        const int cq = fwd::window(kq, nq, wq);
+        const int b1 = fwd::window(i1, nx, w1) * nq + cq;
+        const int b2 = fwd::window(i2, nx, w2) * nq + cq;
+        // partner values: xf_q(x1) for the antiquark, xf_-q(x2) for the quark
+        double f1 = 0.0, f2 = 0.0;
+#pragma unroll
+        for (int jx = 0; jx < 4; ++jx) {
+            double r1 = 0.0, r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                r1 = fma(wq[k], (double)vq[b1 + jx * nq + k], r1);
+                r2 = fma(wq[k], (double)vqb[b2 + jx * nq + k], r2);
+            }
+            f1 = fma(w1[jx], r1, f1);
+            f2 = fma(w2[jx], r2, f2);
+        }
+        const double c = a.scale * a.L2 * a.st_as[p];
+        const double mq = c * f2, mqb = c * f1;
+#pragma unroll
+        for (int jx = 0; jx < 4; ++jx) {
+            const double m1 = mq * w1[jx], m2 = mqb * w2[jx];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                atomicAdd(&gq[b1 + jx * nq + k], m1 * wq[k]);
+                atomicAdd(&gqb[b2 + jx * nq + k], m2 * wq[k]);
+            }
+        }
+    }
+    __syncthreads();
+    double *dq = a.gacc + (size_t)rq * nodes;
+    double *dqb = a.gacc + (size_t)rqb * nodes;
+    for (int e = threadIdx.x; e < nodes; e += kPairBlock) {
+        if (gq[e] != 0.0)
+            unsafeAtomicAdd(&dq[e], gq[e]);
+        if (gqb[e] != 0.0)
+            unsafeAtomicAdd(&dqb[e], gqb[e]);
+    }
+}
+
 }  // namespace
+
+// Pair-wise integrand adjoint (standard parton order, grid fits the
+// double-buffered layout): one workgroup per (point chunk, q), one resident
+// workgroup per compute unit.
+hipError_t launch_dy_pair_adjoint(const DyArgs &a0, bool f32, int cus, hipStream_t s)
+{
+    DyArgs a = a0;
+    int64_t nchunk = cus / 5 > 0 ? cus / 5 : 1;
+    int64_t chunk = (a.n + nchunk - 1) / nchunk;
+    if (chunk < kPairBlock)
+        chunk = kPairBlock;
+    nchunk = (a.n + chunk - 1) / chunk;
+    a.chunk = (int)chunk;
+    auto fn = f32 ? dy_pair_adjoint_kernel<float> : dy_pair_adjoint_kernel<double>;
+    hipLaunchKernelGGL(fn, dim3((unsigned)nchunk, 5u), dim3(kPairBlock), 0, s, a);
+    return hipGetLastError();
+}
 
 bool dy_shape_supported(LaunchShape ls)
 {

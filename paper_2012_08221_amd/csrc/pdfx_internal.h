@@ -240,6 +240,12 @@ size_t dy_lds_layout(DyArgs &a, bool f32, bool *db);
 // by the caller).
 bool dy_dma_supported(int nx, int nq, int na, int nbx, int nbq);
 bool dy_shape_supported(LaunchShape ls);
+// Knot-gradient pass of the integrand backward by quark-antiquark pairs
+// (standard parton order; a.gvals/gstride: borderless group slabs; the state
+// arrays and the zeroed FP64 accumulator as for launch_dy_backward).
+hipError_t launch_dy_pair_adjoint(const DyArgs &a, bool f32, int cus, hipStream_t s);
+hipError_t launch_dy_backward_ex(const DyArgs &a, bool f32, void *grad_xf, int cus,
+                                 hipStream_t s, bool pairs);
 hipError_t launch_dy_dma_forward(const DyArgs &a, bool f32, LaunchShape ls, int cus,
                                  hipStream_t s, int *n_blocks);
 bool set_shape_supported(LaunchShape ls);

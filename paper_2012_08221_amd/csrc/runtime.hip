@@ -1394,7 +1394,20 @@ int pdfx_eval_dy_backward(const pdfx_grid *g, const void *xf_dev, int prec, cons
     a.st_tq = (double *)(ws + o_tq);
     a.st_as = (double *)(ws + o_as);
     a.gacc = (double *)(ws + o_g);
-    e = launch_dy_backward(a, prec == PDFX_F32S, grad_xf, g->cus, (hipStream_t)stream);
+    const bool pairs = dy_dma_ok(g);
+    if (pairs) {
+        // knot-gradient pass by quark-antiquark pairs, from the borderless groups
+        a.gvals = g->dvals[prec].ptr;
+        a.gstride = a.nx * a.nq;
+        if (xf_dev) {
+            if ((e = launch_grp_repack(xf_dev, g->scratch_dvals[prec].ptr, g->nf, a.nx, a.nq,
+                                       g->n_groups[prec], a.gstride, false, prec == PDFX_F32S,
+                                       (hipStream_t)stream)) != hipSuccess)
+                return fail_hip(e, "repack launch");
+            a.gvals = g->scratch_dvals[prec].ptr;
+        }
+    }
+    e = launch_dy_backward_ex(a, prec == PDFX_F32S, grad_xf, g->cus, (hipStream_t)stream, pairs);
     if (e != hipSuccess)
         return fail_hip(e, "integrand backward launch");
     return PDFX_OK;

@@ -181,3 +181,25 @@ def test_integrand_launch_shapes_agree(pdf, prec):
         pdf.set_dy_launch(prec, *keep)
     with pytest.raises(Exception):
         pdf.set_dy_launch(prec, 128, 3)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_integrand_backward_kernels_agree(pdf, api, torch, prec):
+    """The standard grid takes the pair-wise knot-gradient pass, a grid with
+    reversed parton order the per-flavour one: same gradient (FP64 sums in a
+    different order)."""
+    g = cfg0_grid()
+    perm = np.arange(g.pids.size)[::-1].copy()
+    gp = wl.GridSpec(pids=g.pids[perm], x=g.x, q2=g.q2, q_off=g.q_off, xf=g.xf[perm].copy(),
+                     as_q2=g.as_q2, as_val=g.as_val)
+    other = api.mkPDF(gp)
+    u1, u2 = wl.dy_uniforms(5, 300_000)
+    dt = api.prec_dtype(prec)
+    ga = torch.zeros(g.xf.shape, dtype=dt, device="cuda")
+    gb = torch.zeros(g.xf.shape, dtype=dt, device="cuda")
+    api.dy_backward(pdf, u1, u2, ga, XMIN, S, 1e-3, prec=prec)
+    api.dy_backward(other, u1, u2, gb, XMIN, S, 1e-3, prec=prec)
+    a = ga.double().cpu().numpy()
+    b = gb.double().cpu().numpy()[perm]
+    tol = 1e-12 if prec == "f64" else 1e-6
+    np.testing.assert_allclose(a, b, rtol=tol, atol=tol * np.abs(a).max())
