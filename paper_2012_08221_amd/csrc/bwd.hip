@@ -281,7 +281,10 @@ hipError_t launch_backward_ex(const BwdArgs &a0, bool f32, void *grad_xf, double
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     // adjoint pass
-    if (ka.n > 0 && ka.n_u > 0 && (ka.gacc || ka.accx)) {
+    if (ka.n > 0 && ka.n_u > 0 && ka.gacc && !ka.accx && knot_grad_supported(ka.nx, ka.nq)) {
+        if ((e = launch_knot_grad(ka, f32, cus, s)) != hipSuccess)
+            return e;
+    } else if (ka.n > 0 && ka.n_u > 0 && (ka.gacc || ka.accx)) {
         off = 0;
         ka.lds_recx = take((size_t)(ka.ax.n - 1) * 64, 64);
         ka.lds_recq = take((size_t)(ka.aq.n - 1) * 64, 64);

@@ -178,7 +178,88 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
     fwd::wait_vm();
 }
 
+// Knot gradient, dL/dv[f][i][k] = sum_p g[p][f] wx_i(p) wq_k(p), for up to
+// kKnotGroup flavours per workgroup: their FP64 gradient slabs (borderless)
+// sit in LDS together, so each point's state (bins, local coordinates, flags
+// from the state pass) is read and its weights folded once per group rather
+// than once per flavour.  The LDS sums are added to the FP64 accumulator at
+// the end.
+constexpr int kKnotGroup = 3;
+constexpr int kKnotBlock = 1024;
+
+__global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
+{
+    __shared__ double gsl[kKnotGroup][kDmaNodes];
+    const BwdArgs &a = k.b;
+    const int grp = blockIdx.y;
+    const int u0 = grp * kKnotGroup;
+    const int nu = a.n_u - u0 < kKnotGroup ? a.n_u - u0 : kKnotGroup;
+    const int nx = a.nx, nq = a.nq, nodes = nx * nq;
+    for (int e = threadIdx.x; e < nodes; e += kKnotBlock)
+        for (int j = 0; j < kKnotGroup; ++j)
+            gsl[j][e] = 0.0;
+    __syncthreads();
+    const int64_t p_begin = (int64_t)blockIdx.x * a.chunk;
+    const int64_t p_end = p_begin + a.chunk < a.n ? p_begin + a.chunk : a.n;
+    for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kKnotBlock) {
+        if (a.st_flag[p] & 1)   // outside the grid (NaN mode) or NaN input
+            continue;
+        const int idx = a.st_idx[p];
+        const int ix = idx & 0xffff, kq = idx >> 16;
+        const IntervalRec<double> rx = a.ax.rec64[ix];
+        const IntervalRec<double> rq = a.aq.rec64[kq];
+        double wx[4], wq[4];
+        fwd::fold<double>(a.st_tx[p], rx.pl, rx.plql, rx.ql, rx.qr, rx.qrpr, rx.pr, wx);
+        fwd::fold<double>(a.st_tq[p], rq.pl, rq.plql, rq.ql, rq.qr, rq.qrpr, rq.pr, wq);
+        const int base = fwd::window(ix, nx, wx) * nq + fwd::window(kq, nq, wq);
+#pragma unroll
+        for (int j = 0; j < kKnotGroup; ++j) {
+            if (j < nu) {
+                const int u = u0 + j;
+                double g = 0.0;
+                for (int c = a.ucol_off[u]; c < a.ucol_off[u + 1]; ++c)
+                    g += k.f32 ? (double)reinterpret_cast<const float *>(a.gout)[p * a.n_req + a.ucols[c]]
+                               : reinterpret_cast<const double *>(a.gout)[p * a.n_req + a.ucols[c]];
+#pragma unroll
+                for (int jx = 0; jx < 4; ++jx) {
+                    const double gx = g * wx[jx];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+                        atomicAdd(&gsl[j][base + jx * nq + kk], gx * wq[kk]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < nu; ++j) {
+        double *dst = a.gacc + (size_t)a.urow[u0 + j] * nodes;
+        for (int e = threadIdx.x; e < nodes; e += kKnotBlock)
+            if (gsl[j][e] != 0.0)
+                unsafeAtomicAdd(&dst[e], gsl[j][e]);
+    }
+}
+
 }  // namespace
+
+bool knot_grad_supported(int nx, int nq)
+{
+    return nx >= 4 && nq >= 4 && nx * nq <= kDmaNodes;
+}
+
+hipError_t launch_knot_grad(const BwdArgs &b, bool f32, int cus, hipStream_t s)
+{
+    KnotArgs k{b, f32 ? 1 : 0};
+    const int ngroups = (b.n_u + kKnotGroup - 1) / kKnotGroup;
+    int64_t nchunk = cus / ngroups > 0 ? cus / ngroups : 1;   // one workgroup per compute unit
+    int64_t chunk = (b.n + nchunk - 1) / nchunk;
+    if (chunk < kKnotBlock)
+        chunk = kKnotBlock;
+    nchunk = (b.n + chunk - 1) / chunk;
+    k.b.chunk = (int)chunk;
+    hipLaunchKernelGGL(knot_grad_kernel, dim3((unsigned)nchunk, (unsigned)ngroups),
+                       dim3(kKnotBlock), 0, s, k);
+    return hipGetLastError();
+}
 
 hipError_t launch_coord_grad(const CoordArgs &c, bool f32, int cus, hipStream_t s)
 {

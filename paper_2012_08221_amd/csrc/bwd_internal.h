@@ -16,6 +16,16 @@ struct CoordArgs {
 
 hipError_t launch_coord_grad(const CoordArgs &c, bool f32, int cus, hipStream_t s);
 
+// Knot gradient by groups of flavours per workgroup (grids of up to 5000
+// knots, n_x, n_q >= 4): gacc[urow[u]] += sum_p g[p][u] wx wq from the state
+// arrays of b; gacc must be zeroed.
+struct KnotArgs {
+    BwdArgs b;
+    int f32;               // dL/dout is FP32 (else FP64)
+};
+bool knot_grad_supported(int nx, int nq);
+hipError_t launch_knot_grad(const BwdArgs &b, bool f32, int cus, hipStream_t s);
+
 // The adjoint as launch_backward, except that with coords_ready the per-point
 // accumulators accx, accw already hold the coordinate sums (launch_coord_grad)
 // and the flavour workgroups only scatter the knot gradient.

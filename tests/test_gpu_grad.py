@@ -227,13 +227,16 @@ def test_backward_domain_semantics(torch, mods):
     pdf.domain_errors()
 
 
-def test_gradcheck_tiny_fp64(torch, mods):
+@pytest.mark.parametrize("nx", [6, 3])
+def test_gradcheck_tiny_fp64(torch, mods, nx):
+    """nx = 6: the grouped knot and coordinate passes; nx = 3 (fewer than the
+    4 knots a window needs without a border): the per-flavour adjoint."""
     api, ag = mods
     rng = np.random.default_rng(8)
-    xk = np.exp(np.linspace(math.log(1e-3), 0, 6))
+    xk = np.exp(np.linspace(math.log(1e-3), 0, nx))
     qk = np.exp(np.linspace(0, 5, 7))
     g = wl.GridSpec(pids=np.array([21, 1], np.int32), x=xk, q2=qk,
-                    q_off=np.array([0, 7], np.int32), xf=rng.standard_normal((2, 6, 7)))
+                    q_off=np.array([0, 7], np.int32), xf=rng.standard_normal((2, nx, 7)))
     pdf = api.mkPDF(g, with_values=False)
     xq = np.exp(rng.uniform(math.log(1e-3), -0.01, 12))
     qq = np.exp(rng.uniform(0.01, 4.99, 12))
