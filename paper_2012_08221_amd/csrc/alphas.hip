@@ -24,11 +24,17 @@ __global__ __launch_bounds__(kAsBlock) void alphas_kernel(const AlphasArgs a, Ax
     V *out = reinterpret_cast<V *>(a.out);
     const int64_t tile = (int64_t)kAsBlock * kAsPpt;
     for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < a.n; t0 += (int64_t)gridDim.x * tile) {
+        // all of the thread's points first (clamped indices keep these global
+        // loads; a select with a default value would make them flat loads)
+        double qs[kAsPpt];
+#pragma unroll
+        for (int j = 0; j < kAsPpt; ++j)
+            qs[j] = load_point(a.q2, t0 + (int64_t)j * kAsBlock + threadIdx.x, a.n);
 #pragma unroll
         for (int j = 0; j < kAsPpt; ++j) {
             const int64_t p = t0 + (int64_t)j * kAsBlock + threadIdx.x;
             const bool live = p < a.n;
-            double qv = live ? a.q2[p] : a.a.lo;
+            double qv = qs[j];
             const bool nan_in = qv != qv;
             bool ok = true;
             if (!(qv >= a.a.lo && qv <= a.a.hi)) {

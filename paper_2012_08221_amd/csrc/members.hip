@@ -10,6 +10,7 @@
 // flavour loop: stage m's slab for the flavour into LDS, 16-tap stencil,
 // store x f into out[m][p][r].  LDS is sized for the largest member; the
 // slab is single-buffered (a 200 x 80 FP64 slab alone takes 132 KB).
+#include "set_internal.h"
 #include "xfx_fwd_impl.h"
 
 namespace pdfx {
@@ -47,8 +48,17 @@ __global__ __launch_bounds__(BLOCK) void set_kernel(const SetArgs a)
         const int64_t t_first = (int64_t)(item - mi * a.items_per_member) * a.tiles_per_item;
         const MemberDev md = a.mem[m];
         if (m != loaded) {
-            fwd::load_axis<BLOCK>(sm, md.ax, a.lx, F32);
-            fwd::load_axis<BLOCK>(sm, md.aq, a.lq, F32);
+            // member tables through global-address-space loads (the member's
+            // pointers come from device memory)
+            const AxisDev *axes[2] = {&md.ax, &md.aq};
+            const AxisLds *lds[2] = {&a.lx, &a.lq};
+            for (int i = 0; i < 2; ++i) {
+                copy_words_g(sm + lds[i]->knots, axes[i]->knots, axes[i]->n * 8, BLOCK);
+                copy_words_g(sm + lds[i]->seed, axes[i]->seed, axes[i]->nbuckets * 2, BLOCK);
+                copy_words_g(sm + lds[i]->rec64, axes[i]->rec64, (axes[i]->n - 1) * 64, BLOCK);
+                if (F32)
+                    copy_words_g(sm + lds[i]->rec32, axes[i]->rec32, (axes[i]->n - 1) * 32, BLOCK);
+            }
             loaded = m;
             staged = -1;
             __syncthreads();
@@ -101,7 +111,7 @@ __global__ __launch_bounds__(BLOCK) void set_kernel(const SetArgs a)
                 const int row = a.urow[u];
                 if (row != staged) {
                     __syncthreads();
-                    fwd::stage_sync<BLOCK>(slab4, gv + (size_t)row * schunks, schunks);
+                    stage_sync_g(slab4, gv + (size_t)row * schunks, schunks, BLOCK);
                     __syncthreads();
                     staged = row;
                 }

@@ -59,6 +59,26 @@ __device__ __forceinline__ void node_get<float, 4>(const char *p, float *v)
 
 __global__ void reset_cursor(unsigned int *c) { *c = 0u; }
 
+template <typename W>
+__device__ __forceinline__ void weights_g(const AxisDev &ax, int i, double lnv, W w[4]);
+
+template <>
+__device__ __forceinline__ void weights_g<double>(const AxisDev &ax, int i, double lnv, double w[4])
+{
+    gptr<double> r = (gptr<double>)(ax.rec64 + i);   // z, 1/d, pl, pl-ql, ql, qr, qr-pr, pr
+    const double t = (lnv - r[0]) * r[1];
+    fwd::fold<double>(t, r[2], r[3], r[4], r[5], r[6], r[7], w);
+}
+
+template <>
+__device__ __forceinline__ void weights_g<float>(const AxisDev &ax, int i, double lnv, float w[4])
+{
+    gptr<double> r64 = (gptr<double>)(ax.rec64 + i);
+    gptr<float> r = (gptr<float>)(ax.rec32 + i);
+    const float t = (float)((lnv - r64[0]) * r64[1]);
+    fwd::fold<float>(t, r[2], r[3], r[4], r[5], r[6], r[7], w);
+}
+
 template <typename V, int NB, int BLOCK, int PPT>
 __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
 {
@@ -100,11 +120,11 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
         if (n_stage > 0)
             fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);
         if (m != loaded) {
-            fwd::copy_words<BLOCK>(reinterpret_cast<char *>(knots), md.ax.knots, nx * 8);
-            fwd::copy_words<BLOCK>(reinterpret_cast<char *>(knots + nx), md.aq.knots, nq * 8);
-            fwd::copy_words<BLOCK>(reinterpret_cast<char *>(seeds), md.ax.seed, md.ax.nbuckets * 2);
-            fwd::copy_words<BLOCK>(reinterpret_cast<char *>(seeds + md.ax.nbuckets), md.aq.seed,
-                                   md.aq.nbuckets * 2);
+            copy_words_g(reinterpret_cast<char *>(knots), md.ax.knots, nx * 8, BLOCK);
+            copy_words_g(reinterpret_cast<char *>(knots + nx), md.aq.knots, nq * 8, BLOCK);
+            copy_words_g(reinterpret_cast<char *>(seeds), md.ax.seed, md.ax.nbuckets * 2, BLOCK);
+            copy_words_g(reinterpret_cast<char *>(seeds + md.ax.nbuckets), md.aq.seed,
+                         md.aq.nbuckets * 2, BLOCK);
             lx.k = knots;
             lx.seed = seeds;
             lx.n = nx;
@@ -151,8 +171,8 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
                 const double lnx = log(xv), lnq = log(qv);
                 const int ix = fwd::lbin(lx, xv, lnx);
                 const int kq = fwd::lbin(lq, qv, lnq);
-                fwd::weights_gmem<V>(md.ax, ix, lnx, wx[j]);
-                fwd::weights_gmem<V>(md.aq, kq, lnq, wq[j]);
+                weights_g<V>(md.ax, ix, lnx, wx[j]);
+                weights_g<V>(md.aq, kq, lnq, wq[j]);
                 base[j] = fwd::window(ix, nx, wx[j]) * nq + fwd::window(kq, nq, wq[j]);
             }
 

@@ -40,6 +40,33 @@ struct SetDmaArgs {
     int out_pass_pts;          // output rows staged per pass
 };
 
+// The members' table pointers are read from device memory, so the compiler
+// cannot tell that they address global memory and would load through them
+// with flat loads (which also hold up LDS waits); these helpers read through
+// global-address-space pointers instead.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
+__device__ __forceinline__ void copy_words_g(char *dst, const void *src, int bytes, int block)
+{
+    gptr<unsigned long long> s = (gptr<unsigned long long>)src;
+    unsigned long long *d = reinterpret_cast<unsigned long long *>(dst);
+    for (int i = threadIdx.x; i < bytes / 8; i += block)
+        d[i] = s[i];
+}
+
+// A 16-byte-chunk copy of n chunks from global memory (through a
+// global-address-space pointer) into LDS, all threads of the block.
+__device__ __forceinline__ void stage_sync_g(uint4 *dst, const void *src, int n, int block)
+{
+    gptr<unsigned long long> s = (gptr<unsigned long long>)src;
+    unsigned long long *d = reinterpret_cast<unsigned long long *>(dst);
+    for (int c = threadIdx.x; c < n; c += block) {
+        d[2 * c] = s[2 * c];
+        d[2 * c + 1] = s[2 * c + 1];
+    }
+}
+
 // Node bytes the set kernel uses for a member of nx x nq knots with nbx, nbq
 // bucket seeds in a precision (16, 8 or 4), or 0 if it does not fit.
 int set_node_bytes(int nx, int nq, int nbx, int nby, bool f32);
