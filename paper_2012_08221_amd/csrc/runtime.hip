@@ -951,12 +951,12 @@ static std::vector<V> group_slabs_g(const double *xf, int nf, int nx, int nq, in
 }
 
 // Node-width classes of a set for the double-buffered set kernel: per member
-// and precision the widest node (16, 8, 4 bytes) whose slab fits, the group
-// slabs in that width, and the member lists per class.
+// and precision the widest node (16, 8, 4 bytes) whose slab fits, else (FP64)
+// 8-byte nodes with the slab split over both LDS slabs; the group slabs in that
+// width, and the member lists per class.
 static int set_build_classes(pdfx_set *s, const pdfx_grid_desc *members, int n_mem)
 {
     std::vector<SetMemberDev> md(n_mem);
-    const int widths[3] = {16, 8, 4};
     hipError_t e;
     for (int m = 0; m < n_mem; ++m) {
         const pdfx_grid *g = s->members[m];
@@ -964,16 +964,24 @@ static int set_build_classes(pdfx_set *s, const pdfx_grid_desc *members, int n_m
         md[m].aq = g->aq.dev();
         md[m].nx = g->ax.n;
         md[m].nq = g->aq.n;
+        md[m].split_rows = 0;
         for (int p = 0; p < 2; ++p) {
             const bool f32 = p == PDFX_F32S;
-            const int nb = set_node_bytes(g->ax.n, g->aq.n, g->ax.nbuckets, g->aq.nbuckets, f32);
+            int nb = set_node_bytes(g->ax.n, g->aq.n, g->ax.nbuckets, g->aq.nbuckets, f32);
+            int cls = -1;
+            for (int c = 0; c < 3; ++c)
+                if (kSetClassWidth[c] == nb)
+                    cls = c;
+            if (cls < 0 && !f32) {
+                md[m].split_rows = set_split_rows(g->ax.n, g->aq.n, g->ax.nbuckets, g->aq.nbuckets);
+                if (md[m].split_rows > 0) {
+                    nb = 8;
+                    cls = 3;
+                }
+            }
             md[m].nb[p] = nb;
             md[m].gvals[p] = nullptr;
             md[m].gstride[p] = 0;
-            int cls = -1;
-            for (int c = 0; c < 3; ++c)
-                if (widths[c] == nb)
-                    cls = c;
             if (cls < 0) {
                 s->rest_ids[p].push_back(m);
                 continue;
@@ -1001,8 +1009,8 @@ static int set_build_classes(pdfx_set *s, const pdfx_grid_desc *members, int n_m
     if ((e = s->dma_mem.upload(md.data(), md.size() * sizeof(SetMemberDev))) != hipSuccess)
         return fail_hip(e, "upload set descriptors");
     for (int p = 0; p < 2; ++p) {
-        for (int c = 0; c < 4; ++c) {
-            const std::vector<int> &ids = c < 3 ? s->cls_ids[p][c] : s->rest_ids[p];
+        for (int c = 0; c <= kSetClasses; ++c) {
+            const std::vector<int> &ids = c < kSetClasses ? s->cls_ids[p][c] : s->rest_ids[p];
             if (!ids.empty() &&
                 (e = s->ids_dev[p][c].upload(ids.data(), ids.size() * sizeof(int))) != hipSuccess)
                 return fail_hip(e, "upload set work lists");
@@ -1011,9 +1019,25 @@ static int set_build_classes(pdfx_set *s, const pdfx_grid_desc *members, int n_m
     return PDFX_OK;
 }
 
-// LDS layout of the set kernel for the largest member; 0 if it does not fit.
-static size_t set_lds_layout(const pdfx_set *s, bool f32, SetArgs *a)
+// LDS layout of the single-slab set kernel for the largest of the members ids
+// (all members if ids is null); 0 if it does not fit.
+static size_t set_lds_layout(const pdfx_set *s, bool f32, const std::vector<int> *ids,
+                             SetArgs *a)
 {
+    int max_nx = 0, max_nq = 0, max_nbx = 0, max_nbq = 0;
+    size_t max_slab = 0;
+    const int n = ids ? (int)ids->size() : (int)s->members.size();
+    if (n == 0)
+        return 0;
+    for (int i = 0; i < n; ++i) {
+        const pdfx_grid *g = s->members[ids ? (*ids)[i] : i];
+        max_nx = std::max(max_nx, g->ax.n);
+        max_nq = std::max(max_nq, g->aq.n);
+        max_nbx = std::max(max_nbx, g->ax.nbuckets);
+        max_nbq = std::max(max_nbq, g->aq.nbuckets);
+        const int p = f32 ? PDFX_F32S : PDFX_F64;
+        max_slab = std::max(max_slab, (size_t)g->slab_elems[p] * (f32 ? 4 : 8));
+    }
     size_t off = 0;
     auto take = [&](size_t bytes, size_t align) {
         off = (off + align - 1) / align * align;
@@ -1021,15 +1045,15 @@ static size_t set_lds_layout(const pdfx_set *s, bool f32, SetArgs *a)
         off += bytes;
         return (int)r;
     };
-    a->lx.knots = take((size_t)s->max_nx * 8, 16);
-    a->lx.seed = take((size_t)s->max_nbx * 2, 16);
-    a->lx.rec64 = take((size_t)(s->max_nx - 1) * 64, 64);
-    a->lx.rec32 = take(f32 ? (size_t)(s->max_nx - 1) * 32 : 0, 64);
-    a->lq.knots = take((size_t)s->max_nq * 8, 16);
-    a->lq.seed = take((size_t)s->max_nbq * 2, 16);
-    a->lq.rec64 = take((size_t)(s->max_nq - 1) * 64, 64);
-    a->lq.rec32 = take(f32 ? (size_t)(s->max_nq - 1) * 32 : 0, 64);
-    a->lds_slab = take(s->max_slab[f32 ? PDFX_F32S : PDFX_F64], 16);
+    a->lx.knots = take((size_t)max_nx * 8, 16);
+    a->lx.seed = take((size_t)max_nbx * 2, 16);
+    a->lx.rec64 = take((size_t)(max_nx - 1) * 64, 64);
+    a->lx.rec32 = take(f32 ? (size_t)(max_nx - 1) * 32 : 0, 64);
+    a->lq.knots = take((size_t)max_nq * 8, 16);
+    a->lq.seed = take((size_t)max_nbq * 2, 16);
+    a->lq.rec64 = take((size_t)(max_nq - 1) * 64, 64);
+    a->lq.rec32 = take(f32 ? (size_t)(max_nq - 1) * 32 : 0, 64);
+    a->lds_slab = take(max_slab, 16);
     // the kernel's own static __shared__ word sits beside the dynamic region
     return off + 16 <= kLdsLimit ? off : 0;
 }
@@ -1080,13 +1104,9 @@ int pdfx_load_set(const pdfx_grid_desc *members, int32_t n_mem, pdfx_set **out)
         md[m].slab32 = g->slab_elems[PDFX_F32S];
         s->max_nx = std::max(s->max_nx, g->ax.n);
         s->max_nq = std::max(s->max_nq, g->aq.n);
-        s->max_nbx = std::max(s->max_nbx, g->ax.nbuckets);
-        s->max_nbq = std::max(s->max_nbq, g->aq.nbuckets);
-        s->max_slab[PDFX_F64] = std::max(s->max_slab[PDFX_F64], (size_t)md[m].slab64 * 8);
-        s->max_slab[PDFX_F32S] = std::max(s->max_slab[PDFX_F32S], (size_t)md[m].slab32 * 4);
     }
     SetArgs probe{};
-    if (set_lds_layout(s, true, &probe) == 0) {
+    if (set_lds_layout(s, true, nullptr, &probe) == 0) {
         delete s;
         return fail(PDFX_EINVAL, "the largest member does not fit one LDS slab");
     }
@@ -1129,9 +1149,6 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
     if (n_pts == 0)
         return PDFX_OK;
     SetArgs a{};
-    const size_t lds = set_lds_layout(s, prec == PDFX_F32S, &a);
-    if (lds == 0)
-        return fail(PDFX_EINVAL, "the largest member does not fit LDS in this precision");
     a.mem = (const MemberDev *)s->mem_desc.ptr;
     a.n_mem = (int)s->members.size();
     a.n_req = n_req;
@@ -1169,15 +1186,14 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
     // aligned member blocks, and a request whose groups fit every class's
     // result slots.  The other members (or all, otherwise) go through the
     // single-slab kernel.
-    const int widths[3] = {16, 8, 4};
-    SetDmaArgs d[3];
+    SetDmaArgs d[kSetClasses];
     bool dma = set_dma_shape_supported(ls) && (uintptr_t)out % 16 == 0 &&
                (n_pts * n_req * (f32 ? 4 : 8)) % 16 == 0;
-    for (int c = 0; c < 3 && dma; ++c) {
+    for (int c = 0; c < kSetClasses && dma; ++c) {
         if (s->cls_ids[prec][c].empty())
             continue;
         XfxArgs plan = fa;
-        if (!plan_stages(plan, widths[c] / (f32 ? 4 : 8))) {
+        if (!plan_stages(plan, kSetClassWidth[c] / (f32 ? 4 : 8))) {
             dma = false;
             break;
         }
@@ -1214,17 +1230,25 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
             pass = tile_pts;
         da.out_pass_pts = (int)pass;
     }
+    // the single-slab kernel takes the members outside the classes (all of
+    // them without the classes) and needs each one's slab in LDS
+    const size_t lds = set_lds_layout(s, f32, dma ? &s->rest_ids[prec] : nullptr, &a);
+    if (lds == 0 && (!dma || !s->rest_ids[prec].empty()))
+        return fail(PDFX_EINVAL, "a member does not fit LDS in this precision%s",
+                    dma ? "" : " (members beyond one slab need the double-buffered classes: "
+                               "16-byte aligned output blocks and a set launch shape they "
+                               "are compiled for)");
     if (dma) {
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < kSetClasses; ++c) {
             if (s->cls_ids[prec][c].empty())
                 continue;
-            if ((e = launch_set_dma(d[c], f32, widths[c], ls, s->cus, (hipStream_t)stream)) !=
-                hipSuccess)
+            if ((e = launch_set_dma(d[c], f32, kSetClassWidth[c], c == 3, ls, s->cus,
+                                    (hipStream_t)stream)) != hipSuccess)
                 return fail_hip(e, "set launch");
         }
         if (s->rest_ids[prec].empty())
             return PDFX_OK;
-        a.mem_ids = (const int *)s->ids_dev[prec][3].ptr;
+        a.mem_ids = (const int *)s->ids_dev[prec][kSetClasses].ptr;
         a.n_items = (int)(s->rest_ids[prec].size() * ipm);
     }
     e = launch_set(a, f32, ls, lds, s->cus, (hipStream_t)stream);

@@ -8,6 +8,7 @@
 
 #include "../../include/pdfx.h"
 #include "pdfx_internal.h"
+#include "set_internal.h"
 
 namespace pdfx {
 
@@ -96,16 +97,15 @@ struct pdfx_set {
     pdfx::DeviceBuf mem_desc;                // MemberDev[n_mem]
     pdfx::DeviceBuf counter;                 // work-list cursor
     pdfx::DeviceBuf dom_count;
-    int max_nx = 0, max_nq = 0, max_nbx = 0, max_nbq = 0;
-    size_t max_slab[2] = {0, 0};             // bytes per precision
     pdfx::LaunchShape shape[2] = {{512, 2}, {512, 2}};
     int tiles_per_item[2] = {4, 4};
     int cus = 256;
     // double-buffered classes (set_dma.hip): members by node width, per precision
     pdfx::DeviceBuf dma_mem;                 // SetMemberDev[n_mem]
     std::vector<pdfx::DeviceBuf *> dma_vals; // group slabs of every member and precision
-    std::vector<int> cls_ids[2][3];          // members of node width 16, 8, 4 bytes
+    int max_nx = 0, max_nq = 0;              // largest member grid (tuning key)
+    std::vector<int> cls_ids[2][pdfx::kSetClasses];   // members per class (node width 16, 8, 4, split 8)
     std::vector<int> rest_ids[2];            // members left to the single-slab kernel
-    pdfx::DeviceBuf ids_dev[2][4];           // the lists above on the device
+    pdfx::DeviceBuf ids_dev[2][pdfx::kSetClasses + 1];   // the lists above on the device
     ~pdfx_set();
 };

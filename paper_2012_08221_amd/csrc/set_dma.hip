@@ -79,7 +79,10 @@ __device__ __forceinline__ void weights_g<float>(const AxisDev &ax, int i, doubl
     fwd::fold<float>(t, r[2], r[3], r[4], r[5], r[6], r[7], w);
 }
 
-template <typename V, int NB, int BLOCK, int PPT>
+// SPLIT (FP64, 8-byte nodes): the member's group slab is too large for one
+// LDS slab; its rows [0, split_rows) go to slab0 and the rest to slab1, so a
+// stage holds one group in both slabs, copied while no stencil runs.
+template <typename V, int NB, int BLOCK, int PPT, bool SPLIT>
 __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
 {
     constexpr int G = NB / (int)sizeof(V);
@@ -117,8 +120,18 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
         const int chunks = (nx * nq * NB + 15) / 16;   // 16-byte chunks per slab
         const uint4 *gsrc = reinterpret_cast<const uint4 *>(md.gvals[prec]);
         const size_t gstride = (size_t)md.gstride[prec] * NB / 16;   // chunks per group
+        // split layout: rows below r_split in slab0, the others in slab1
+        const int r_split = SPLIT ? md.split_rows : nx;
+        const int chunks0 = SPLIT ? r_split * nq * NB / 16 : chunks;   // r_split * nq is even
+        const int chunks1 = SPLIT ? chunks - chunks0 : 0;
+        auto load_group = [&](int grp) {
+            const uint4 *src = gsrc + (size_t)grp * gstride;
+            fwd::dma_slab<BLOCK>(slab0, src, chunks0);
+            if (SPLIT)
+                fwd::dma_slab<BLOCK>(slab1, src + chunks0, chunks1);
+        };
         if (n_stage > 0)
-            fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);
+            load_group(a.sgrp[0]);
         if (m != loaded) {
             copy_words_g(reinterpret_cast<char *>(knots), md.ax.knots, nx * 8, BLOCK);
             copy_words_g(reinterpret_cast<char *>(knots + nx), md.aq.knots, nq * 8, BLOCK);
@@ -145,8 +158,12 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
         for (int64_t tile = t_first; tile < t_end; ++tile) {
             const int64_t t0 = tile * tile_pts;
             const bool more = tile + 1 < t_end;
+            if (SPLIT && tile > t_first && n_stage > 0) {
+                __syncthreads();   // the previous tile's output rows have left slab1
+                load_group(a.sgrp[0]);
+            }
             V wx[PPT][4], wq[PPT][4];
-            int base[PPT];
+            int base[PPT], brow[PPT];
             bool ok[PPT];
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
@@ -173,7 +190,10 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
                 const int kq = fwd::lbin(lq, qv, lnq);
                 weights_g<V>(md.ax, ix, lnx, wx[j]);
                 weights_g<V>(md.aq, kq, lnq, wq[j]);
-                base[j] = fwd::window(ix, nx, wx[j]) * nq + fwd::window(kq, nq, wq[j]);
+                brow[j] = fwd::window(ix, nx, wx[j]);
+                base[j] = fwd::window(kq, nq, wq[j]);   // column; the row is brow
+                if (!SPLIT)
+                    base[j] += brow[j] * nq;
             }
 
             fwd::wait_vm();
@@ -184,16 +204,30 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
             for (int s = 0; s < NS; ++s) {
                 if (s < n_stage) {
                     const bool last = s + 1 == n_stage;
-                    const char *cur = reinterpret_cast<const char *>((s & 1) ? slab1 : slab0);
-                    uint4 *const nxt = (s & 1) ? slab0 : slab1;
-                    if (!last)
-                        fwd::dma_slab<BLOCK>(nxt, gsrc + (size_t)a.sgrp[s + 1] * gstride, chunks);
+                    const char *cur = reinterpret_cast<const char *>((s & 1) && !SPLIT ? slab1 : slab0);
+                    if (SPLIT && s > 0) {
+                        __syncthreads();   // the previous group's stencils are done
+                        load_group(a.sgrp[s]);
+                        fwd::wait_vm();
+                        __syncthreads();
+                    }
+                    if (!SPLIT && !last)
+                        fwd::dma_slab<BLOCK>((s & 1) ? slab0 : slab1,
+                                             gsrc + (size_t)a.sgrp[s + 1] * gstride, chunks);
 #pragma unroll
                     for (int j = 0; j < PPT; ++j) {
                         V acc[G];
 #pragma unroll
                         for (int jx = 0; jx < 4; ++jx) {
-                            const char *rowp = cur + (size_t)(base[j] + jx * nq) * NB;
+                            const char *rowp;
+                            if (SPLIT) {
+                                const int r = brow[j] + jx;
+                                const bool hi = r >= r_split;
+                                rowp = reinterpret_cast<const char *>(hi ? slab1 : slab0) +
+                                       (size_t)((hi ? r - r_split : r) * nq + base[j]) * NB;
+                            } else {
+                                rowp = cur + (size_t)(base[j] + jx * nq) * NB;
+                            }
                             V r[G];
 #pragma unroll
                             for (int k = 0; k < 4; ++k) {
@@ -211,7 +245,7 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
                         for (int g = 0; g < G; ++g)
                             res[j][s * G + g] = ok[j] ? acc[g] : fwd::quiet_nan<V>();
                     }
-                    if (!last) {
+                    if (!SPLIT && !last) {
                         fwd::wait_vm();
                         __syncthreads();
                     }
@@ -242,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
                     }
                 }
                 __syncthreads();
-                if (pa + a.out_pass_pts >= valid && n_stage > 1 && more)
+                if (!SPLIT && pa + a.out_pass_pts >= valid && n_stage > 1 && more)
                     fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);
                 const int bytes = pn * n_req * (int)sizeof(V);
                 char *dst = reinterpret_cast<char *>(out + (t0 + pa) * n_req);   // 16-byte aligned
@@ -259,7 +293,7 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
 
 constexpr LaunchShape kSetDmaShapes[] = {{512, 1}, {512, 2}, {256, 2}};
 
-template <typename V, int NB>
+template <typename V, int NB, bool SPLIT = false>
 hipError_t launch_typed(const SetDmaArgs &a, LaunchShape ls, int cus, hipStream_t s)
 {
     auto go = [&](auto fn, int block) -> hipError_t {
@@ -273,15 +307,27 @@ hipError_t launch_typed(const SetDmaArgs &a, LaunchShape ls, int cus, hipStream_
         return hipGetLastError();
     };
     if (ls.block == 512 && ls.ppt == 1)
-        return go(set_dma_kernel<V, NB, 512, 1>, 512);
+        return go(set_dma_kernel<V, NB, 512, 1, SPLIT>, 512);
     if (ls.block == 512 && ls.ppt == 2)
-        return go(set_dma_kernel<V, NB, 512, 2>, 512);
+        return go(set_dma_kernel<V, NB, 512, 2, SPLIT>, 512);
     if (ls.block == 256 && ls.ppt == 2)
-        return go(set_dma_kernel<V, NB, 256, 2>, 256);
+        return go(set_dma_kernel<V, NB, 256, 2, SPLIT>, 256);
     return hipErrorInvalidValue;
 }
 
 }  // namespace
+
+int set_split_rows(int nx, int nq, int nbx, int nbq)
+{
+    if (nx < 4 || nq < 4 || nx + nq > kSetKnots || nbx + nbq > kSetSeeds)
+        return 0;
+    int r = kSetSlabBytes / (nq * 8);
+    if ((r * nq) % 2)
+        --r;   // slab0 ends on a 16-byte chunk
+    if (r < 1 || r >= nx || (nx - r) * nq * 8 > kSetSlabBytes)
+        return 0;
+    return r;
+}
 
 int set_node_bytes(int nx, int nq, int nbx, int nbq, bool f32)
 {
@@ -307,9 +353,11 @@ bool set_dma_shape_supported(LaunchShape ls)
     return false;
 }
 
-hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, LaunchShape ls, int cus,
-                          hipStream_t s)
+hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, bool split, LaunchShape ls,
+                          int cus, hipStream_t s)
 {
+    if (split)
+        return !f32 && nb == 8 ? launch_typed<double, 8, true>(a, ls, cus, s) : hipErrorInvalidValue;
     if (f32) {
         if (nb == 16)
             return launch_typed<float, 16>(a, ls, cus, s);

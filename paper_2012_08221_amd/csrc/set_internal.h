@@ -11,6 +11,11 @@ constexpr int kSetSlabBytes = 78016;
 constexpr int kSetKnots = 320;
 constexpr int kSetSeeds = 1280;
 
+// Classes of the double-buffered set kernel by node bytes; the last is the
+// FP64 class whose slab is split over both LDS slabs.
+constexpr int kSetClasses = 4;
+constexpr int kSetClassWidth[kSetClasses] = {16, 8, 4, 8};
+
 // One member as the double-buffered set kernel sees it.
 struct SetMemberDev {
     AxisDev ax, aq;
@@ -18,6 +23,7 @@ struct SetMemberDev {
     int gstride[2];         // nodes per group, per precision (node bytes * gstride % 16 == 0)
     int nb[2];              // node bytes per precision (16, 8 or 4); 0: not in a class
     int nx, nq;
+    int split_rows;         // FP64 split class: rows held in the first slab (else 0)
 };
 
 struct SetDmaArgs {
@@ -71,9 +77,15 @@ __device__ __forceinline__ void stage_sync_g(uint4 *dst, const void *src, int n,
 // bucket seeds in a precision (16, 8 or 4), or 0 if it does not fit.
 int set_node_bytes(int nx, int nq, int nbx, int nby, bool f32);
 
-// Launches the class kernel of node width nb over args' work list.
-hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, LaunchShape ls, int cus,
-                          hipStream_t s);
+// For an FP64 member too large for set_node_bytes: the rows of its 8-byte
+// group slab held in the first LDS slab when the slab is split over both (the
+// rest fitting the second), or 0 if it does not fit that way either.
+int set_split_rows(int nx, int nq, int nbx, int nbq);
+
+// Launches the class kernel of node width nb (split: the FP64 split class)
+// over args' work list.
+hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, bool split, LaunchShape ls,
+                          int cus, hipStream_t s);
 bool set_dma_shape_supported(LaunchShape ls);
 
 }  // namespace pdfx

@@ -119,3 +119,43 @@ def test_set_domain_and_pid_requests(pset, members):
     for k in (0, 60):
         ora = oracle.xfx(members[k], [21], x, q2, mode=1)
         np.testing.assert_allclose(outc[k], ora, rtol=1e-12)
+
+
+def test_large_members_split_slab(torch):
+    """Members whose FP64 group slab needs both LDS slabs (rows split between
+    them; odd n_q moves the split one row down), one at the largest grid that
+    split fits, and a small one, on random points and on points at every x
+    knot around the split row.  A member beyond the split (230 x 90) is too
+    large for any FP64 kernel and raises; in FP32 it takes the single-slab
+    kernel beside the class kernels."""
+    from paper_2012_08221_amd import api
+    from paper_2012_08221_amd.binding import PdfxError
+    p = wl.draw_params(np.random.default_rng(3))
+    geo = [(200, 79), (200, 81), (240, 80), (60, 30), (230, 90)]
+    mems = [wl.make_grid(p * (1 + 0.01 * k), nx, wl.MEMBER_EDGES[3], nq, with_alphas=False)
+            for k, (nx, nq) in enumerate(geo)]
+    x, q2 = wl.queries(5, 8_000)
+    for m in mems[:4]:
+        r = 78016 // (m.n_q * 8)
+        kx = m.x[max(r - 6, 0):r + 6]
+        mid = np.sqrt(kx[1:] * kx[:-1])
+        qs = np.geomspace(m.q2[0], m.q2[-1], 7)
+        xe, qe = np.meshgrid(np.concatenate([kx, mid]), qs)
+        x = np.concatenate([x, xe.ravel()])
+        q2 = np.concatenate([q2, qe.ravel()])
+    n = x.size - x.size % 2   # 16-byte aligned FP64 output blocks
+    x, q2 = x[:n], q2[:n]
+    pids = mems[0].pids
+    fit = api.PDFSet(mems[:4])
+    for prec in ("f64", "f32s"):
+        out = fit.xfxQ2(pids, x, q2, prec=prec).double().cpu().numpy()
+        for k, m in enumerate(mems[:4]):
+            e, tol = check_member(m, out[k], x, q2, pids, prec)
+            assert e <= tol, (prec, k, e, tol)
+    big = api.PDFSet(mems)
+    with pytest.raises(PdfxError, match="does not fit LDS"):
+        big.xfxQ2(pids, x, q2, prec="f64")
+    out = big.xfxQ2(pids, x, q2, prec="f32s").double().cpu().numpy()
+    for k, m in enumerate(mems):
+        e, tol = check_member(m, out[k], x, q2, pids, "f32s")
+        assert e <= tol, ("f32s", k, e, tol)
