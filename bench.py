@@ -61,6 +61,18 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def forward_kernel_sources():
     """Sources of the forward kernels (any change voids recorded counters)."""
     import glob
@@ -141,13 +153,19 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    if args.calib_copy:
-        n = 1 << 27                                   # 1 GiB of FP64 in, 1 GiB out
+    def copy_gbs():
+        """HBM bandwidth a plain copy reaches: 1 GiB of FP64 read, 1 GiB written."""
+        n = 1 << 27
         a = torch.ones(n, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         ms = timed(lambda: torch.mul(a, 1.0, out=b), 5)
+        del a, b
+        return n, ms, 2 * n * 8 / ms / 1e6
+
+    if args.calib_copy:
+        n, ms, gbs = copy_gbs()
         print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8,
-                          "ms": ms, "gbs": 2 * n * 8 / ms / 1e6}))
+                          "ms": ms, "gbs": gbs}))
         return
 
     grid = wl.config0_grid()
@@ -323,8 +341,9 @@ def main():
     bytes_per_pt = 16 + nf * (8 if args.prec == "f64" else 4)
     achieved = n * bytes_per_pt / (head["xfx_ms"] * 1e-3) / 1e9
 
-    # CPU baseline: the oracle on the host cores over the workload's points,
-    # and the GPU error on its first 1e6 points
+    # CPU baseline: the oracle on the host cores over the workload's points
+    # (median of 3), one thread on a 1e5-point sample, and stated samples of the
+    # members and integrand workloads; the GPU error on the first 1e6 points
     cpu = None
     err = {}
     if not args.no_cpu:
@@ -332,12 +351,38 @@ def main():
         nc = n
         threads = oracle.default_threads()
         log("oracle on %d points, %d threads" % (nc, threads))
+        walls = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ora = oracle.xfx(grid, pids, x_np[:nc], q2_np[:nc], nthreads=threads)
+            walls.append(time.perf_counter() - t0)
+        dt = sorted(walls)[1]
+        n1 = min(nc, 100_000)
         t0 = time.perf_counter()
-        ora = oracle.xfx(grid, pids, x_np[:nc], q2_np[:nc], nthreads=threads)
-        dt = time.perf_counter() - t0
+        oracle.xfx(grid, pids, x_np[:n1], q2_np[:n1], nthreads=1)
+        dt1 = time.perf_counter() - t0
         cpu = {"value": nc * nf / dt, "unit": "pf/s", "cores": threads, "kind": "oracle",
-               "sample": "all %d points x %d flavours of the step, FP64, %.2f s wall"
-                         % (nc, nf, dt)}
+               "sample": "all %d points x %d flavours of the step, FP64, median of 3: %.2f s wall"
+                         % (nc, nf, dt),
+               "cpu_model": cpu_model(),
+               "one_thread": {"value": n1 * nf / dt1, "unit": "pf/s",
+                              "sample": "first %d points, FP64" % n1}}
+        if not args.no_extra:
+            members = wl.member_grids(101)
+            xs, qs = wl.queries(2, 100_000)
+            t0 = time.perf_counter()
+            for m in members:
+                oracle.xfx(m, m.pids, xs, qs, nthreads=threads)
+            dtm = time.perf_counter() - t0
+            cpu["members"] = {"value": 101 * xs.size * nf / dtm, "unit": "pf/s",
+                              "sample": "101 members x 1e5 points x 11 flavours, FP64"}
+            u1, u2 = wl.dy_uniforms(0, 10_000_000)
+            t0 = time.perf_counter()
+            oracle.dy(grid, u1, u2, wl.DY_XMIN, wl.SQRT_S_DY ** 2, nthreads=threads)
+            dtd = time.perf_counter() - t0
+            cpu["drell_yan"] = {"value": u1.size / dtd, "unit": "points/s",
+                                "sample": "one 1e7-point chunk (seed of chunk 0), FP64 forward"}
+            log("oracle: members %.2f s, integrand chunk %.2f s" % (dtm, dtd))
         ns = min(nc, 1_000_000)
         M = oracle.stencil_absmax(grid, pids, x_np[:ns], q2_np[:ns])
         for prec, r in results.items():
@@ -363,6 +408,7 @@ def main():
                                      "peak_gbs": LDS_PEAK_GBS,
                                      "frac": lb / (r["xfx_ms"] * 1e-3) / 1e9 / LDS_PEAK_GBS}
 
+    copy = copy_gbs()[2]
     rec = {
         "metric": METRIC,
         "value": value,
@@ -385,6 +431,7 @@ def main():
                      "traffic": recorded_traffic(args.prec, head["launch"]),
                      "kernel": forward_kernel_name(args.prec, head["launch"]),
                      "bytes_per_point": bytes_per_pt,
+                     "copy_gbs": copy, "frac_of_copy": achieved / copy,
                      "lds": variants.get(args.prec, {}).get("lds")},
         "cpu_baseline": cpu,
         "variants": variants,
