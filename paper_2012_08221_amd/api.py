@@ -145,15 +145,26 @@ class PDF:
     alphas_trace = trace
 
 
-def mkPDF(spec, with_values: bool = True) -> PDF:
-    """Build a PDF object for one member (the paper's mkPDF, Sec. 2.1)."""
+def mkPDF(spec, dirname: str | None = None, with_values: bool = True) -> PDF:
+    """Build a PDF object for one member (the paper's mkPDF, Sec. 2.1, Fig. 1,
+    Fig. 4): spec is a grid object (pids, x, q2, q_off, xf, optional alpha_s
+    knots) or a set member named 'NAME/M' read from the standard grid folders
+    under dirname (else LHAPDF_DATA_PATH)."""
+    if isinstance(spec, str):
+        from . import lhapdf
+        spec = lhapdf.load_member(spec, dirname)
     return PDF(spec, with_values)
 
 
 class PDFSet:
-    """Many members (uneven grids, shared pid list) evaluated in one launch."""
+    """Many members (uneven grids, shared pid list) evaluated in one launch;
+    specs is a list of grid objects or the name of a set in the standard grid
+    folders (every member; dirname as for mkPDF)."""
 
-    def __init__(self, specs):
+    def __init__(self, specs, dirname: str | None = None):
+        if isinstance(specs, str):
+            from . import lhapdf
+            specs = lhapdf.load_set(specs, dirname)
         self._descs = [B.HostDesc(s.pids, s.x, s.q2, s.q_off, s.xf) for s in specs]
         self.handle = B.pdfx_load_set(self._descs)
         self.n_mem = len(specs)
