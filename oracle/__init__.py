@@ -127,6 +127,46 @@ def alphas(as_q2, as_val, q2, mode: int = 0, nthreads: int | None = None) -> np.
     return out
 
 
+def lumi(grid, pid_a, pid_b, x1, x2, q2, coef=None, mode: int = 0,
+         nthreads: int | None = None):
+    """Flavour-pair luminosity of the integrand of Eq. (1) (Sec. 3.1; the
+    single-top example of Fig. 4 divides the PDF products by x1 x2):
+
+        L[p, k] = f_{pid_a[k]}(x1[p], q2[p]) * f_{pid_b[k]}(x2[p], q2[p]),  f = xf / x,
+        S[p]    = sum_k coef[k] * L[p, k]     (coef None: all 1).
+
+    q2 is an array or a scalar.  mode 0: NaN where x1, x2 or q2 is outside
+    the grid; mode 1: every coordinate clamped to the grid edge, x included in
+    f = xf / x.  A pair with a pid absent from the grid is 0.  Returns (L, S).
+    """
+    pid_a = np.atleast_1d(np.asarray(pid_a, dtype=np.int32))
+    pid_b = np.atleast_1d(np.asarray(pid_b, dtype=np.int32))
+    x1, x2 = _f64(x1), _f64(x2)
+    q2 = np.broadcast_to(np.asarray(q2, dtype=np.float64), x1.shape).copy()
+    xlo, xhi = float(np.min(grid.x)), float(np.max(grid.x))
+    qlo, qhi = float(np.min(grid.q2)), float(np.max(grid.q2))
+    bad = ~((x1 >= xlo) & (x1 <= xhi) & (x2 >= xlo) & (x2 <= xhi) & (q2 >= qlo) & (q2 <= qhi))
+    if mode == 1:
+        nan_in = np.isnan(x1) | np.isnan(x2) | np.isnan(q2)
+        x1 = np.where(nan_in, x1, np.clip(x1, xlo, xhi))
+        x2 = np.where(nan_in, x2, np.clip(x2, xlo, xhi))
+        q2 = np.where(nan_in, q2, np.clip(q2, qlo, qhi))
+        bad = nan_in
+    fa = xfx(grid, pid_a, x1, q2, mode, nthreads) / x1[:, None]
+    fb = xfx(grid, pid_b, x2, q2, mode, nthreads) / x2[:, None]
+    L = fa * fb
+    L[bad, :] = np.nan
+    present = set(int(p) for p in grid.pids)
+    canon = lambda p: 21 if p == 0 else p  # noqa: E731  (gluon id 0 or 21)
+    pset = set(canon(p) for p in present)
+    for k in range(pid_a.shape[0]):
+        if canon(int(pid_a[k])) not in pset or canon(int(pid_b[k])) not in pset:
+            L[:, k] = 0.0
+    c = np.ones(pid_a.shape[0]) if coef is None else np.asarray(coef, dtype=np.float64)
+    S = L @ c
+    return L, S
+
+
 def dy(grid, u1, u2, xmin: float, s: float, nthreads: int | None = None) -> np.ndarray:
     """Per-point LO Drell-Yan-like integrand I(u1, u2) (see pdf_oracle.c)."""
     lib = _load()
