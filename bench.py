@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline step")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
-    ap.add_argument("--only", default=None, choices=["xfx", "members", "dy", "bwd"],
+    ap.add_argument("--only", default=None, choices=["xfx", "members", "dy", "bwd", "lumi"],
                     help="run one workload for a few steps (profiler runs) and print its timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain copy kernel of known size (counter scaling) and exit")
@@ -133,6 +133,7 @@ def main():
         sys.exit(2)
     import torch
     from paper_2012_08221_amd import api, autograd as ag
+    from paper_2012_08221_amd import binding as B
     from paper_2012_08221_amd import workloads as wl
 
     dev = torch.device("cuda:0")
@@ -334,6 +335,48 @@ def main():
         variants["drell_yan"] = {"n_points": nchunk * csize, "chunk": csize, **dres}
         if args.only == "dy":
             print(json.dumps({"only": "dy", **variants["drell_yan"]}))
+            return
+
+    # flavour-pair luminosity, the single-top pattern of Fig. 4: b at x1
+    # against u, c, dbar, sbar at x2, Q^2 = m_t^2, 1e7 points
+    if args.only == "lumi" or (args.only is None and not args.no_extra):
+        nl = 10_000_000
+        g = torch.Generator(device=dev)
+        g.manual_seed(201208226)
+        lo = float(np.log(1e-5))
+        x1 = torch.exp(lo - lo * torch.rand(nl, generator=g, dtype=torch.float64, device=dev))
+        x2 = torch.exp(lo - lo * torch.rand(nl, generator=g, dtype=torch.float64, device=dev))
+        pa, pb = [5, 5, 5, 5], [2, 4, -1, -3]
+        lres = {}
+        for prec in ("f64", "f32s"):
+            dt = api.prec_dtype(prec)
+            S = torch.empty(nl, dtype=dt, device=dev)
+            L = torch.empty((nl, 4), dtype=dt, device=dev)
+            code = api.prec_code(prec)
+
+            def run_sum():
+                B.pdfx_eval_lumi(pdf.handle, None, code, pa, pb, None, x1.data_ptr(),
+                                 x2.data_ptr(), None, 172.5 ** 2, nl, None, S.data_ptr(), 0,
+                                 stream.cuda_stream)
+
+            def run_both():
+                B.pdfx_eval_lumi(pdf.handle, None, code, pa, pb, None, x1.data_ptr(),
+                                 x2.data_ptr(), None, 172.5 ** 2, nl, L.data_ptr(), S.data_ptr(),
+                                 0, stream.cuda_stream)
+            ms_s = timed(run_sum, 5)
+            ms_b = timed(run_both, 5)
+            vb = 8 if prec == "f64" else 4
+            lres[prec] = {"sum_ms": ms_s, "sum_points_per_s": nl / (ms_s * 1e-3),
+                          "sum_hbm_gbs_algorithmic": nl * (16 + vb) / ms_s / 1e6,
+                          "pairs_and_sum_ms": ms_b,
+                          "pairs_and_sum_hbm_gbs_algorithmic": nl * (16 + 5 * vb) / ms_b / 1e6}
+            log("lumi %s: sum %.3f ms, pairs+sum %.3f ms" % (prec, ms_s, ms_b))
+            del S, L
+        variants["lumi"] = {"n_points": nl, "pairs": [list(t) for t in zip(pa, pb)],
+                            "q2": 172.5 ** 2, "launch_shape": list(pdf.lumi_launch("f64")),
+                            **lres}
+        if args.only == "lumi":
+            print(json.dumps({"only": "lumi", **variants["lumi"]}))
             return
 
     head = results[args.prec]

@@ -200,6 +200,36 @@ int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 int pdfx_get_dy_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
 int pdfx_set_dy_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 
+/* ---- flavour-pair luminosity (Eq. 1; the single-top example of Fig. 4) ---- */
+
+/* For pairs k = 0 .. n_pair-1 of partons (pid_a[k] at x1, pid_b[k] at x2):
+ *   L_k(p) = f_{pid_a[k]}(x1[p], Q2_p) * f_{pid_b[k]}(x2[p], Q2_p),  f = xf / x,
+ *   S(p)   = sum_k coef[k] * L_k(p)        (coef NULL: every c_k = 1),
+ * with Q2_p = q2[p], or q2_fixed for every point when q2 is NULL.  This is
+ * the luminosity an integrand multiplies by its matrix elements; per-pair L
+ * lets the caller weight each pair per point.
+ * g: a grid that fits the double-buffered kernel (n_x, n_q >= 4, at most 5000
+ * knots); xf_dev: caller values [n_flav][n_x][n_q] of the precision, or NULL
+ * for the owned ones.  pid_a, pid_b, coef: host arrays of n_pair (1 .. 128).
+ * x1, x2, q2: device FP64 [n]; out_pair: device [n][n_pair] or NULL; out_sum:
+ * device [n] or NULL (not both NULL when n > 0); outputs FP64 or FP32 by
+ * precision.
+ * A pair with a parton absent from the grid gives 0.  A point with x1, x2 or
+ * Q2 outside the grid gives NaN in NAN mode (and is counted), or is evaluated
+ * at the clamped point in CLAMP mode (f = xf / x at the clamped x).  The pairs
+ * may touch at most 6 flavour groups in FP64 (2 partons each in grid order)
+ * and 3 in FP32 (4 each): every pair of an 11-parton grid qualifies.
+ * Asynchronous on stream. */
+int pdfx_eval_lumi(const pdfx_grid *g, const void *xf_dev, int prec, int32_t n_pair,
+                   const int32_t *pid_a, const int32_t *pid_b, const double *coef,
+                   const double *x1, const double *x2, const double *q2, double q2_fixed,
+                   int64_t n, void *out_pair, void *out_sum, int domain_mode, void *stream);
+
+/* Launch shape of the luminosity kernel per precision (default (512, 2));
+ * compiled: (512, 1), (512, 2), (256, 2). */
+int pdfx_get_lumi_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
+int pdfx_set_lumi_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
+
 /* ---- diagnostics ---- */
 
 /* Number of out-of-grid points counted since the last call, over all eval

@@ -126,6 +126,34 @@ class PDF:
     def set_dy_launch(self, prec, block, ppt):
         B.pdfx_set_dy_launch(self.handle, prec_code(prec), block, ppt)
 
+    def lumi_launch(self, prec="f64"):
+        return B.pdfx_get_lumi_launch(self.handle, prec_code(prec))
+
+    def set_lumi_launch(self, prec, block, ppt):
+        B.pdfx_set_lumi_launch(self.handle, prec_code(prec), block, ppt)
+
+    def lumi(self, pid_a, pid_b, x1, x2, q2=None, q2_fixed=None, coef=None, prec="f64",
+             pairs=True, total=True, domain="nan", values=None):
+        """Flavour-pair luminosity (Eq. 1; Fig. 4's single-top example):
+        L[p, k] = f_{pid_a[k]}(x1[p], Q2) f_{pid_b[k]}(x2[p], Q2) with f = xf / x
+        and S[p] = sum_k coef[k] L[p, k], at Q2 = q2[p] or q2_fixed.
+        Returns (L or None, S or None)."""
+        x1 = _device_f64(x1)
+        x2 = _device_f64(x2, x1.device)
+        q2t = None if q2 is None else _device_f64(q2, x1.device)
+        if q2t is None and q2_fixed is None:
+            raise ValueError("give q2 or q2_fixed")
+        pid_a = np.atleast_1d(np.asarray(pid_a, dtype=np.int32))
+        n = x1.numel()
+        dt = prec_dtype(prec)
+        L = torch.empty((n, pid_a.shape[0]), dtype=dt, device=x1.device) if pairs else None
+        S = torch.empty(n, dtype=dt, device=x1.device) if total else None
+        B.pdfx_eval_lumi(self.handle, _ptr(values), prec_code(prec), pid_a, pid_b, coef,
+                         x1.data_ptr(), x2.data_ptr(), _ptr(q2t),
+                         0.0 if q2_fixed is None else q2_fixed, n, _ptr(L), _ptr(S),
+                         _DOMAIN[domain], _stream(x1.device))
+        return L, S
+
     def autotune(self, prec="f64", n_req=None, n_pts=1 << 22, cache_path=None):
         B.pdfx_autotune(self.handle, prec_code(prec), n_req or self.n_flav, n_pts, cache_path)
         return self.launch(prec)

@@ -41,6 +41,7 @@ EXPORTS = (
     "pdfx_eval_set_xfx", "pdfx_eval_dy", "pdfx_dy_max_blocks", "pdfx_eval_dy_backward",
     "pdfx_autotune", "pdfx_autotune_set", "pdfx_get_launch", "pdfx_set_launch",
     "pdfx_get_dy_launch", "pdfx_set_dy_launch",
+    "pdfx_eval_lumi", "pdfx_get_lumi_launch", "pdfx_set_lumi_launch",
     "pdfx_domain_errors", "pdfx_last_error", "pdfx_version",
 )
 
@@ -101,6 +102,10 @@ def lib():
             "pdfx_set_launch": ([vp, i32, i32, i32], i32),
             "pdfx_get_dy_launch": ([vp, i32, vp, vp], i32),
             "pdfx_set_dy_launch": ([vp, i32, i32, i32], i32),
+            "pdfx_eval_lumi": ([vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, dbl, i64, vp, vp, i32,
+                                vp], i32),
+            "pdfx_get_lumi_launch": ([vp, i32, vp, vp], i32),
+            "pdfx_set_lumi_launch": ([vp, i32, i32, i32], i32),
             "pdfx_domain_errors": ([vp, vp], i32),
             "pdfx_last_error": ([], ctypes.c_char_p),
             "pdfx_version": ([], ctypes.c_char_p),
@@ -249,6 +254,31 @@ def pdfx_get_dy_launch(h, prec):
 
 def pdfx_set_dy_launch(h, prec, block, ppt):
     return check(lib().pdfx_set_dy_launch(h, prec, block, ppt))
+
+
+def pdfx_eval_lumi(h, xf_dev, prec, pid_a, pid_b, coef, x1, x2, q2, q2_fixed, n, out_pair,
+                   out_sum, domain_mode, stream):
+    """pid_a, pid_b, coef: host sequences (coef may be None); device pointers as ints."""
+    a, pa = _pids(pid_a)
+    b, pb = _pids(pid_b)
+    if a.shape != b.shape:
+        raise ValueError("pid_a and pid_b differ in length")
+    c = None if coef is None else np.ascontiguousarray(coef, dtype=np.float64)
+    if c is not None and c.shape != a.shape:
+        raise ValueError("coef and the pid lists differ in length")
+    return check(lib().pdfx_eval_lumi(h, xf_dev, prec, a.shape[0], pa, pb,
+                                      None if c is None else c.ctypes.data, x1, x2, q2,
+                                      float(q2_fixed), n, out_pair, out_sum, domain_mode, stream))
+
+
+def pdfx_get_lumi_launch(h, prec):
+    b, p = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().pdfx_get_lumi_launch(h, prec, ctypes.byref(b), ctypes.byref(p)))
+    return b.value, p.value
+
+
+def pdfx_set_lumi_launch(h, prec, block, ppt):
+    return check(lib().pdfx_set_lumi_launch(h, prec, block, ppt))
 
 
 def pdfx_domain_errors(h) -> int:

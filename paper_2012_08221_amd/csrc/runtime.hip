@@ -12,6 +12,7 @@
 #include "../../include/pdfx.h"
 #include "pdfx_internal.h"
 #include "runtime_internal.h"
+#include "lumi_internal.h"
 #include "bwd_internal.h"
 #include "set_internal.h"
 
@@ -436,6 +437,32 @@ int pdfx_set_dy_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
     if (!dy_shape_supported(ls))
         return fail(PDFX_EINVAL, "integrand launch shape (%d, %d) not compiled", block, ppt);
     g->dy_shape[prec] = ls;
+    return PDFX_OK;
+}
+
+int pdfx_get_lumi_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt)
+{
+    clear_error();
+    if (!g || !block || !ppt)
+        return fail(PDFX_EINVAL, "NULL argument");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    *block = g->lumi_shape[prec].block;
+    *ppt = g->lumi_shape[prec].ppt;
+    return PDFX_OK;
+}
+
+int pdfx_set_lumi_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
+{
+    clear_error();
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    LaunchShape ls{block, ppt};
+    if (!lumi_shape_supported(ls))
+        return fail(PDFX_EINVAL, "luminosity launch shape (%d, %d) not compiled", block, ppt);
+    g->lumi_shape[prec] = ls;
     return PDFX_OK;
 }
 
@@ -1434,6 +1461,117 @@ int pdfx_eval_dy_backward(const pdfx_grid *g, const void *xf_dev, int prec, cons
     e = launch_dy_backward_ex(a, prec == PDFX_F32S, grad_xf, g->cus, (hipStream_t)stream, pairs);
     if (e != hipSuccess)
         return fail_hip(e, "integrand backward launch");
+    return PDFX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Flavour-pair luminosity
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int pdfx_eval_lumi(const pdfx_grid *g, const void *xf_dev, int prec, int32_t n_pair,
+                   const int32_t *pid_a, const int32_t *pid_b, const double *coef,
+                   const double *x1, const double *x2, const double *q2, double q2_fixed,
+                   int64_t n, void *out_pair, void *out_sum, int domain_mode, void *stream)
+{
+    using namespace pdfx;
+    clear_error();
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (prec != PDFX_F64 && prec != PDFX_F32S)
+        return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    if (!xf_dev && !g->has_values)
+        return fail(PDFX_ENOVALUES, "grid has no owned values and xf_dev is NULL");
+    if (n_pair < 1 || n_pair > kLumiMaxPairs)
+        return fail(PDFX_EINVAL, "n_pair = %d outside [1, %d]", n_pair, kLumiMaxPairs);
+    if (!pid_a || !pid_b)
+        return fail(PDFX_EINVAL, "pid_a or pid_b is NULL");
+    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP)
+        return fail(PDFX_EINVAL, "unknown domain mode %d", domain_mode);
+    if (n < 0)
+        return fail(PDFX_EINVAL, "n < 0");
+    if (n > 0 && !out_pair && !out_sum)
+        return fail(PDFX_EINVAL, "out_pair and out_sum are both NULL");
+    if (!q2 && !(q2_fixed > 0.0 && std::isfinite(q2_fixed)))
+        return fail(PDFX_EINVAL, "q2 is NULL and q2_fixed is not positive and finite");
+    if (coef)
+        for (int k = 0; k < n_pair; ++k)
+            if (!std::isfinite(coef[k]))
+                return fail(PDFX_EINVAL, "coef[%d] is not finite", k);
+    const bool f32 = prec == PDFX_F32S;
+    const size_t vs = f32 ? 4 : 8;
+    if (((uintptr_t)x1 & 7) || ((uintptr_t)x2 & 7) || ((uintptr_t)q2 & 7) ||
+        ((uintptr_t)out_pair & (vs - 1)) || ((uintptr_t)out_sum & (vs - 1)))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    if (!g->dma_grid || !lumi_supported(g->ax.n, g->aq.n, g->ax.nbuckets, g->aq.nbuckets))
+        return fail(PDFX_EINVAL, "grid %dx%d does not fit the luminosity kernel's LDS slabs",
+                    g->ax.n, g->aq.n);
+    if (n == 0)
+        return PDFX_OK;
+    if (!x1 || !x2)
+        return fail(PDFX_EINVAL, "x1 or x2 is NULL");
+
+    // Stage plan: the flavour groups holding a parton of some pair, in grid
+    // order, each with the side(s) it is evaluated at; slot s*G+g of a row.
+    const int G = f32 ? 4 : 2;
+    const int ng = g->n_groups[prec];
+    std::vector<int> side_of_group(ng, 0), stage_of_group(ng, -1);
+    std::vector<int> ra(n_pair), rb(n_pair);
+    for (int k = 0; k < n_pair; ++k) {
+        ra[k] = g->row_of(pid_a[k]);
+        rb[k] = g->row_of(pid_b[k]);
+        if (ra[k] < 0 || rb[k] < 0)
+            continue;   // a pair with an absent parton is 0
+        side_of_group[ra[k] / G] |= 1;
+        side_of_group[rb[k] / G] |= 2;
+    }
+    LumiArgs a{};
+    for (int gi = 0; gi < ng; ++gi) {
+        if (side_of_group[gi]) {
+            if (a.n_stage == kGrpMaxSlots / G)
+                return fail(PDFX_EINVAL, "the pairs touch more than %d flavour groups of %d",
+                            kGrpMaxSlots / G, G);
+            stage_of_group[gi] = a.n_stage;
+            a.sgrp[a.n_stage] = gi;
+            a.side[a.n_stage] = side_of_group[gi];
+            ++a.n_stage;
+        }
+    }
+    a.n_pair = n_pair;
+    for (int k = 0; k < n_pair; ++k) {
+        const bool live = ra[k] >= 0 && rb[k] >= 0;
+        a.ia[k] = live ? stage_of_group[ra[k] / G] * G + ra[k] % G : -1;
+        a.ib[k] = live ? stage_of_group[rb[k] / G] * G + rb[k] % G : -1;
+        a.coef[k] = coef ? coef[k] : 1.0;
+    }
+    a.ax = g->ax.dev();
+    a.aq = g->aq.dev();
+    a.nx = g->ax.n;
+    a.nq = g->aq.n;
+    a.gstride = a.nx * a.nq;
+    a.gvals = g->dvals[prec].ptr;
+    hipError_t e;
+    if (xf_dev) {
+        if ((e = launch_grp_repack(xf_dev, g->scratch_dvals[prec].ptr, g->nf, a.nx, a.nq,
+                                   g->n_groups[prec], a.gstride, false, f32,
+                                   (hipStream_t)stream)) != hipSuccess)
+            return fail_hip(e, "repack launch");
+        a.gvals = g->scratch_dvals[prec].ptr;
+    }
+    a.x1 = x1;
+    a.x2 = x2;
+    a.q2 = q2;
+    a.q2_fixed = q2_fixed;
+    a.n = n;
+    a.out_pair = out_pair;
+    a.out_sum = out_sum;
+    a.domain_mode = domain_mode;
+    a.dom_count = (unsigned long long *)g->dom_count.ptr;
+    if ((e = launch_lumi(a, f32, g->lumi_shape[prec], g->cus, (hipStream_t)stream)) != hipSuccess)
+        return fail_hip(e, "luminosity launch");
     return PDFX_OK;
 }
 

@@ -72,6 +72,7 @@ struct pdfx_grid {
     pdfx::DeviceBuf dom_count;               // unsigned long long
     pdfx::LaunchShape shape[2];              // per precision
     pdfx::LaunchShape dy_shape[2] = {{512, 1}, {512, 2}};   // double-buffered integrand kernel
+    pdfx::LaunchShape lumi_shape[2] = {{512, 2}, {512, 2}};  // flavour-pair luminosity kernel
     mutable pdfx::DeviceBuf bwd_ws;          // adjoint workspace (grows on demand)
     // resident-workgroup cache per [precision][kernel: per-flavour, grouped, double-buffered]
     mutable pdfx::LaunchShape occ_shape[2][3] = {};

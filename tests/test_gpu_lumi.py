@@ -1,0 +1,164 @@
+"""Flavour-pair luminosity kernel (pdfx_eval_lumi) against the oracle:
+L_k = f_a(x1) f_b(x2) with f = xf / x and S = sum_k c_k L_k.
+
+Error metric: each factor is judged like the forward evaluation (capped
+relative error against max(|xf|, 0.1 M), M the largest knot in its stencil),
+so a product is judged against the product of those scales and the sum
+against sum_k |c_k| times them.  The bounds add the factors' bounds."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import f32_tolerance
+from paper_2012_08221_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+MT2 = 172.5 ** 2
+SINGLE_TOP = ([5, 5, 5, 5], [2, 4, -1, -3])   # b at x1 against u, c, dbar, sbar at x2
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def grid():
+    return wl.config0_grid()
+
+
+@pytest.fixture(scope="module")
+def pdf(torch, grid):
+    from paper_2012_08221_amd import api
+    return api.mkPDF(grid)
+
+
+def points(k, n):
+    rng = np.random.default_rng(201208221 + 100 + k)
+    lo = np.log(1e-5)
+    x1 = np.exp(lo + rng.random(n) * -lo)
+    x2 = np.exp(lo + rng.random(n) * -lo)
+    q2 = np.exp(rng.uniform(np.log(4.0), np.log(1e8), n))
+    return x1, x2, q2
+
+
+def scales(grid, pa, pb, x1, x2, q2, coef):
+    q2 = np.broadcast_to(q2, x1.shape)
+    fa = oracle.xfx(grid, pa, x1, q2)
+    fb = oracle.xfx(grid, pb, x2, q2)
+    ma = oracle.stencil_absmax(grid, pa, x1, q2)
+    mb = oracle.stencil_absmax(grid, pb, x2, q2)
+    sk = np.maximum(np.abs(fa), 0.1 * ma) * np.maximum(np.abs(fb), 0.1 * mb) / (x1 * x2)[:, None]
+    c = np.ones(len(pa)) if coef is None else np.abs(np.asarray(coef, dtype=np.float64))
+    return sk, sk @ c
+
+
+def check(grid, L, S, pa, pb, x1, x2, q2, coef, tol, mode=0):
+    Lo, So = oracle.lumi(grid, pa, pb, x1, x2, q2, coef=coef, mode=mode)
+    if mode == 1:   # scales at the clamped point
+        x1 = np.clip(x1, grid.x[0], grid.x[-1])
+        x2 = np.clip(x2, grid.x[0], grid.x[-1])
+        q2 = np.clip(q2, grid.q2[0], grid.q2[-1])
+    sk, ss = scales(grid, pa, pb, x1, x2, q2, coef)
+    # no scale where the point is outside (NaN there) or the pair is absent
+    # (0 on both sides): unit scale
+    sk = np.where((sk == 0) | np.isnan(sk), 1.0, sk)
+    ss = np.where((ss == 0) | np.isnan(ss), 1.0, ss)
+    if L is not None:
+        np.testing.assert_array_equal(np.isnan(L), np.isnan(Lo))
+        ok = ~np.isnan(Lo)
+        e = (np.abs(L - Lo) / sk)[ok]
+        assert e.size == 0 or e.max() <= tol, e.max()
+    if S is not None:
+        np.testing.assert_array_equal(np.isnan(S), np.isnan(So))
+        ok = ~np.isnan(So)
+        e = (np.abs(S - So) / ss)[ok]
+        assert e.size == 0 or e.max() <= tol, e.max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_single_top_fixed_scale(pdf, grid, prec):
+    x1, x2, _ = points(0, 100_000)
+    L, S = pdf.lumi(*SINGLE_TOP, x1, x2, q2_fixed=MT2, prec=prec)
+    tol = 2e-12 if prec == "f64" else 2 * f32_tolerance(grid) + 1e-6
+    check(grid, L.double().cpu().numpy(), S.double().cpu().numpy(), *SINGLE_TOP, x1, x2, MT2,
+          None, tol)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_full_pair_matrix_per_point_scale(pdf, grid, prec):
+    """All 121 pairs of the 11 partons (every group at both sides), signed
+    weights, per-point Q^2, a ragged count spanning several tiles."""
+    pids = list(grid.pids)
+    pa = [a for a in pids for _ in pids]
+    pb = [b for _ in pids for b in pids]
+    coef = np.random.default_rng(3).normal(size=len(pa))
+    n = 12_345
+    x1, x2, q2 = points(1, n)
+    L, S = pdf.lumi(pa, pb, x1, x2, q2=q2, coef=coef, prec=prec)
+    tol = 2e-12 if prec == "f64" else 2 * f32_tolerance(grid) + len(pa) * 2.4e-7
+    check(grid, L.double().cpu().numpy(), S.double().cpu().numpy(), pa, pb, x1, x2, q2, coef, tol)
+
+
+def test_launch_shapes_and_outputs_agree(pdf, torch):
+    """Every compiled shape gives the same bits; pairs-only and sum-only calls
+    give the same bits as both together."""
+    x1, x2, q2 = points(2, 30_001)
+    pa, pb = [1, 2, 21, -5, 3], [-1, -2, 21, 5, 4]
+    ref = None
+    for prec in ("f64", "f32s"):
+        for shape in ((512, 1), (512, 2), (256, 2)):
+            pdf.set_lumi_launch(prec, *shape)
+            L, S = pdf.lumi(pa, pb, x1, x2, q2=q2, coef=[1, 2, 3, 4, 5], prec=prec)
+            got = (L.cpu().numpy(), S.cpu().numpy())
+            if shape == (512, 1):
+                ref = got
+            np.testing.assert_array_equal(got[0], ref[0])
+            np.testing.assert_array_equal(got[1], ref[1])
+        L1, _ = pdf.lumi(pa, pb, x1, x2, q2=q2, coef=[1, 2, 3, 4, 5], prec=prec, total=False)
+        _, S1 = pdf.lumi(pa, pb, x1, x2, q2=q2, coef=[1, 2, 3, 4, 5], prec=prec, pairs=False)
+        np.testing.assert_array_equal(L1.cpu().numpy(), ref[0])
+        np.testing.assert_array_equal(S1.cpu().numpy(), ref[1])
+        pdf.set_lumi_launch(prec, 512, 2)
+
+
+def test_absent_duplicate_gluon_and_domain(pdf, grid, torch):
+    x1 = np.array([1e-3, 1e-3, 2.0, 1e-3, np.nan, 0.3, 1e-12, 0.5])
+    x2 = np.array([0.2, 0.2, 0.2, 0.2, 0.2, 0.3, 0.1, 1e-4])
+    q2 = np.array([100.0, 1e12, 100.0, 100.0, 100.0, 1.0, 50.0, 3.0])
+    pa, pb = [1, 7, 21, 1, 0], [-1, 1, 6, -1, 21]   # absent 7 and 6; a repeated pair; gluon 0
+    pdf.domain_errors()
+    L, S = pdf.lumi(pa, pb, x1, x2, q2=q2, coef=[1.0, 5.0, 7.0, 2.0, 0.5])
+    check(grid, L.cpu().numpy(), S.cpu().numpy(), pa, pb, x1, x2, q2,
+          [1.0, 5.0, 7.0, 2.0, 0.5], 2e-12)
+    assert pdf.domain_errors() == 4      # Q^2 above, x1 above, NaN x1, x1 below
+    L, S = pdf.lumi(pa, pb, x1, x2, q2=q2, coef=[1.0, 5.0, 7.0, 2.0, 0.5], domain="clamp")
+    check(grid, L.cpu().numpy(), S.cpu().numpy(), pa, pb, x1, x2, q2,
+          [1.0, 5.0, 7.0, 2.0, 0.5], 2e-12, mode=1)
+    assert pdf.domain_errors() == 1      # only the NaN input
+
+
+def test_caller_values_and_empty(pdf, grid, torch):
+    from paper_2012_08221_amd import api
+    x1, x2, q2 = points(4, 5000)
+    vals = torch.as_tensor(grid.xf, device="cuda")
+    for prec, dt in (("f64", torch.float64), ("f32s", torch.float32)):
+        a = pdf.lumi(*SINGLE_TOP, x1, x2, q2=q2, prec=prec)
+        b = pdf.lumi(*SINGLE_TOP, x1, x2, q2=q2, prec=prec, values=vals.to(dt).contiguous())
+        np.testing.assert_array_equal(a[0].cpu().numpy(), b[0].cpu().numpy())
+        np.testing.assert_array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+    L, S = pdf.lumi(*SINGLE_TOP, np.zeros(0), np.zeros(0), q2_fixed=MT2)
+    assert L.shape == (0, 4) and S.shape == (0,)
+    from paper_2012_08221_amd.binding import PdfxError
+    with pytest.raises(PdfxError, match="q2_fixed"):
+        pdf.lumi(*SINGLE_TOP, x1, x2, q2_fixed=-1.0)
+    with pytest.raises(PdfxError, match="n_pair"):
+        pdf.lumi([], [], x1, x2, q2_fixed=MT2)
+    big = wl.make_grid(wl.draw_params(np.random.default_rng(1)), 120, wl.MEMBER_EDGES[3], 60,
+                       with_alphas=False)
+    with pytest.raises(PdfxError, match="luminosity kernel"):
+        api.mkPDF(big).lumi(*SINGLE_TOP, x1, x2, q2_fixed=MT2)
