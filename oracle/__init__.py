@@ -127,6 +127,63 @@ def alphas(as_q2, as_val, q2, mode: int = 0, nthreads: int | None = None) -> np.
     return out
 
 
+def _continue(f0, f1, u):
+    """Continuation from the edge value f0 through the next knot's f1, u in
+    units of that knot step (u <= 0 outside): power law (linear in ln|f| against
+    the log coordinate) when f1 / f0 > 0, else linear in the log coordinate."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = f1 / f0
+        pw = f0 * np.exp(u * np.log(np.where(r > 0, r, 1.0)))
+    return np.where((f0 != 0) & (r > 0), pw, f0 + u * (f1 - f0))
+
+
+def xfx_extrapolated(grid, pids, x, q2, nthreads: int | None = None) -> np.ndarray:
+    """x f with continuation outside the grid (the out-of-grid reading of the
+    library's EXTRAPOLATE mode; inside the grid it is xfx itself).
+
+    Along an axis the edge knot e and the next knot n inward give F_e and F_n
+    (the interpolation evaluated at those knot coordinates, the other
+    coordinate as queried); beyond the edge, with u = ln(z/z_e) / ln(z_n/z_e),
+    xf = F_e (F_n/F_e)^u if F_n/F_e > 0, else F_e + u (F_n - F_e).  Outside in
+    both x and Q^2: continue in x at the two Q^2 edge knots, then in Q^2.
+    NaN inputs give NaN.
+    """
+    rp = np.atleast_1d(np.asarray(pids, dtype=np.int32))
+    x, q2 = _f64(x), _f64(q2)
+    out = xfx(grid, rp, x, q2, 0, nthreads)
+    gx, gq = np.asarray(grid.x, dtype=np.float64), np.asarray(grid.q2, dtype=np.float64)
+    xo = (x < gx[0]) | (x > gx[-1])
+    qo = (q2 < gq[0]) | (q2 > gq[-1])
+    sel = (xo | qo) & ~np.isnan(x) & ~np.isnan(q2)
+    if not sel.any():
+        return out
+    xs, qs, xos, qos = x[sel], q2[sel], xo[sel], qo[sel]
+    low_x = xs < gx[0]
+    xe = np.where(low_x, gx[0], gx[-1])
+    xn = np.where(low_x, gx[1], gx[-2])
+    low_q = qs < gq[0]
+    qe = np.where(low_q, gq[0], gq[-1])
+    qn = np.where(low_q, gq[1], gq[-2])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ux = np.log(xs / xe) / np.log(xn / xe)
+        uq = np.log(qs / qe) / np.log(qn / qe)
+    ev = lambda xx, qq: xfx(grid, rp, xx, qq, 0, nthreads)  # noqa: E731
+    res = np.empty((xs.shape[0], rp.shape[0]))
+    m = xos & ~qos                      # x outside only
+    if m.any():
+        res[m] = _continue(ev(xe[m], qs[m]), ev(xn[m], qs[m]), ux[m][:, None])
+    m = qos & ~xos                      # Q^2 outside only
+    if m.any():
+        res[m] = _continue(ev(xs[m], qe[m]), ev(xs[m], qn[m]), uq[m][:, None])
+    m = xos & qos                       # both
+    if m.any():
+        a = _continue(ev(xe[m], qe[m]), ev(xn[m], qe[m]), ux[m][:, None])
+        b = _continue(ev(xe[m], qn[m]), ev(xn[m], qn[m]), ux[m][:, None])
+        res[m] = _continue(a, b, uq[m][:, None])
+    out[sel] = res
+    return out
+
+
 def lumi(grid, pid_a, pid_b, x1, x2, q2, coef=None, mode: int = 0,
          nthreads: int | None = None):
     """Flavour-pair luminosity of the integrand of Eq. (1) (Sec. 3.1; the
