@@ -226,6 +226,20 @@ def main():
             print(json.dumps({"only": "xfx", "prec": args.prec, "xfx_ms": r["xfx_ms"]}))
             return
 
+        # EXTRAPOLATE mode on the same points with 1% of them moved below the
+        # grid's x range (one decade): the forward pass plus the continuation
+        if args.only is None and not args.no_extra:
+            xe = x.clone()
+            xe[::100] = float(grid.x[0]) * 0.1
+            oute = torch.empty((n, nf), dtype=torch.float64, device=dev)
+            ms_e = timed(lambda: pdf.xfxQ2(pids, xe, q2, out=oute, domain="extrapolate"), 5)
+            ms_c = timed(lambda: pdf.xfxQ2(pids, xe, q2, out=oute, domain="clamp"), 5)
+            variants["extrapolate"] = {"n_points": n, "outside_fraction": 0.01, "f64_ms": ms_e,
+                                       "f64_clamp_ms": ms_c,
+                                       "continuation_ms": ms_e - ms_c}
+            log("extrapolate f64: %.3f ms (clamp %.3f ms)" % (ms_e, ms_c))
+            del xe, oute
+
     # forward + backward: loss = sum w * xf on 1e6 points, grid as an FP32 tensor
     if args.only == "bwd" or (args.only is None and not args.no_extra):
         nb = 1_000_000

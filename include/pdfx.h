@@ -26,7 +26,13 @@
  *  - Points outside the grid: PDFX_DOMAIN_NAN writes NaN for every column of
  *    that point and counts the point (pdfx_domain_errors); PDFX_DOMAIN_CLAMP
  *    evaluates at the point clamped to the grid edge (and counts nothing,
- *    except NaN inputs, which give NaN and are counted in both modes).
+ *    except NaN inputs, which give NaN and are counted in every mode).
+ *    PDFX_DOMAIN_EXTRAPOLATE (pdfx_eval_xfx and pdfx_eval_xfxQ only)
+ *    continues beyond an edge from the edge knot e through the next knot n
+ *    inward, with F_e, F_n the interpolation at those knot coordinates and
+ *    u = ln(z/z_e) / ln(z_n/z_e): xf = F_e (F_n/F_e)^u if F_n/F_e > 0, else
+ *    F_e + u (F_n - F_e); outside in x and Q^2 alike, x first, then Q^2.
+ *    It counts only NaN inputs.  The other calls reject it.
  *  - Ties: a Q^2 equal to a subgrid threshold uses the upper subgrid; a
  *    query on the last knot of an axis uses the last interval.
  */
@@ -76,7 +82,7 @@ enum pdfx_status {
  *            FMAs, values and outputs FP32. */
 enum pdfx_prec { PDFX_F64 = 0, PDFX_F32S = 1 };
 
-enum pdfx_domain { PDFX_DOMAIN_NAN = 0, PDFX_DOMAIN_CLAMP = 1 };
+enum pdfx_domain { PDFX_DOMAIN_NAN = 0, PDFX_DOMAIN_CLAMP = 1, PDFX_DOMAIN_EXTRAPOLATE = 2 };
 
 /* Maximum number of requested pids in one call. */
 #define PDFX_MAX_REQ 64

@@ -17,7 +17,8 @@ from . import binding as B
 
 _PREC = {"f64": B.PDFX_F64, "fp64": B.PDFX_F64, "f32s": B.PDFX_F32S, "fp32": B.PDFX_F32S,
          "f32": B.PDFX_F32S}
-_DOMAIN = {"nan": B.PDFX_DOMAIN_NAN, "clamp": B.PDFX_DOMAIN_CLAMP}
+_DOMAIN = {"nan": B.PDFX_DOMAIN_NAN, "clamp": B.PDFX_DOMAIN_CLAMP,
+           "extrapolate": B.PDFX_DOMAIN_EXTRAPOLATE}
 
 
 def prec_code(prec) -> int:

@@ -24,6 +24,7 @@ PDFX_F64 = 0
 PDFX_F32S = 1
 PDFX_DOMAIN_NAN = 0
 PDFX_DOMAIN_CLAMP = 1
+PDFX_DOMAIN_EXTRAPOLATE = 2
 PDFX_MAX_REQ = 64
 
 # Launch shapes (workgroup size, points per thread) compiled into the forward

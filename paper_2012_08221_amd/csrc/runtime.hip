@@ -13,6 +13,7 @@
 #include "pdfx_internal.h"
 #include "runtime_internal.h"
 #include "lumi_internal.h"
+#include "extrap_internal.h"
 #include "bwd_internal.h"
 #include "set_internal.h"
 
@@ -314,12 +315,45 @@ static int eval_xfx_common(const pdfx_grid *g, const void *xf_dev, int prec, con
                            void *out, int domain_mode, void *stream, int q_is_q)
 {
     clear_error();
+    // EXTRAPOLATE: the forward pass in clamp mode, then the continuation
+    // rewrites the rows of the points outside the grid
+    const bool extrap = domain_mode == PDFX_DOMAIN_EXTRAPOLATE;
     XfxArgs a;
-    int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q, n_pts, out, domain_mode, &a);
+    int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q, n_pts, out,
+                              extrap ? PDFX_DOMAIN_CLAMP : domain_mode, &a);
     if (rc != PDFX_OK || n_pts == 0)
         return rc;
     a.q_is_q = q_is_q;
-    return run_xfx(g, a, xf_dev, prec, (hipStream_t)stream);
+    rc = run_xfx(g, a, xf_dev, prec, (hipStream_t)stream);
+    if (rc != PDFX_OK || !extrap)
+        return rc;
+    if ((uintptr_t)out & (prec == PDFX_F64 ? 7 : 3))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    ExtrapArgs e{};
+    e.ax = g->ax.dev();
+    e.aq = g->aq.dev();
+    e.vals = g->vals[prec].ptr;
+    e.nx = g->ax.n;
+    e.nq = g->aq.n;
+    e.slab_elems = g->slab_elems[prec];
+    e.n_req = n_req;
+    for (int r = 0; r < n_req; ++r)
+        e.row[r] = g->row_of(pids[r]);
+    e.x = x;
+    e.q = q;
+    e.q_is_q = q_is_q;
+    e.out = out;
+    e.n = n_pts;
+    hipError_t he;
+    if (xf_dev) {
+        RepackArgs r{xf_dev, g->scratch_vals[prec].ptr, g->nf, e.nx, e.nq, e.slab_elems};
+        if ((he = launch_repack(r, prec == PDFX_F32S, (hipStream_t)stream)) != hipSuccess)
+            return fail_hip(he, "repack launch");
+        e.vals = g->scratch_vals[prec].ptr;
+    }
+    if ((he = launch_extrap(e, prec == PDFX_F32S, g->cus, (hipStream_t)stream)) != hipSuccess)
+        return fail_hip(he, "continuation launch");
+    return PDFX_OK;
 }
 
 int pdfx_eval_xfx(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
@@ -684,6 +718,9 @@ int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int
         return fail(PDFX_EINVAL, "grid is NULL");
     if (prec != PDFX_F64 && prec != PDFX_F32S)
         return fail(PDFX_EINVAL, "unknown precision %d", prec);
+    if (domain_mode == PDFX_DOMAIN_EXTRAPOLATE)
+        return fail(PDFX_EINVAL, "domain mode EXTRAPOLATE applies to pdfx_eval_xfx and "
+                                 "pdfx_eval_xfxQ only");
     if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP)
         return fail(PDFX_EINVAL, "unknown domain mode %d", domain_mode);
     if (n_req < 1 || n_req > PDFX_MAX_REQ)

@@ -1,0 +1,111 @@
+"""Domain mode EXTRAPOLATE of pdfx_eval_xfx against the oracle's continuation
+(oracle.xfx_extrapolated): points beyond every edge and corner, mixed with
+inside points, which must keep the plain interpolation's bits."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import capped_rel_err, f32_tolerance
+from paper_2012_08221_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def grid():
+    return wl.config0_grid()
+
+
+@pytest.fixture(scope="module")
+def pdf(torch, grid):
+    from paper_2012_08221_amd import api
+    return api.mkPDF(grid)
+
+
+def outside_points(grid, n, k, reach):
+    """n points: a third inside, the rest beyond the x and/or Q^2 edges by up
+    to `reach` decades."""
+    rng = np.random.default_rng(201208221 + 300 + k)
+    x, q2 = wl.queries(10 + k, n)
+    lx0, lx1 = np.log10(grid.x[0]), np.log10(grid.x[-1])
+    lq0, lq1 = np.log10(grid.q2[0]), np.log10(grid.q2[-1])
+    kind = rng.integers(0, 6, n)
+    d = rng.uniform(1e-3, reach, n)
+    x = np.where(kind == 1, 10 ** (lx0 - d), x)
+    x = np.where(kind == 2, 10 ** (lx1 + 0.1 * d / reach), x)            # just above x = 1
+    q2 = np.where(kind == 3, 10 ** (lq0 - d), q2)
+    q2 = np.where(kind == 4, 10 ** (lq1 + d), q2)
+    x = np.where(kind == 5, 10 ** (lx0 - d), x)
+    q2 = np.where(kind == 5, np.where(rng.random(n) < 0.5, 10 ** (lq0 - d), 10 ** (lq1 + d)), q2)
+    return x, q2
+
+
+def err(grid, got, ora, pids, x, q2):
+    xc = np.clip(x, grid.x[0], grid.x[-1])
+    qc = np.clip(q2, grid.q2[0], grid.q2[-1])
+    M = oracle.stencil_absmax(grid, pids, xc, qc)
+    np.testing.assert_array_equal(np.isnan(got), np.isnan(ora))
+    ok = ~np.isnan(ora)
+    return capped_rel_err(got[ok], ora[ok], M[ok]).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_continuation_matches_oracle(pdf, grid, prec):
+    pids = list(grid.pids) + [7]                   # 7 is absent: 0 everywhere
+    reach = 3.0 if prec == "f64" else 0.5
+    x, q2 = outside_points(grid, 20_001, 0, reach)
+    got = pdf.xfxQ2(pids, x, q2, prec=prec, domain="extrapolate").double().cpu().numpy()
+    ora = oracle.xfx_extrapolated(grid, pids, x, q2)
+    assert np.all(got[:, -1] == 0)
+    # FP32: the stencil bound, times how far the continuation carries it
+    # (half a decade is |u| up to about 2.4 per axis, compounded at corners)
+    tol = 1e-12 if prec == "f64" else 12 * f32_tolerance(grid)
+    assert err(grid, got, ora, pids, x, q2) <= tol
+
+
+def test_inside_points_keep_their_bits_and_counter(pdf, grid, torch):
+    pids = list(grid.pids)
+    x, q2 = outside_points(grid, 30_000, 1, 2.0)
+    inside = (x >= grid.x[0]) & (x <= grid.x[-1]) & (q2 >= grid.q2[0]) & (q2 <= grid.q2[-1])
+    x[:3], q2[:3] = np.nan, 10.0                     # NaN inputs
+    pdf.domain_errors()
+    for prec in ("f64", "f32s"):
+        e = pdf.xfxQ2(pids, x, q2, prec=prec, domain="extrapolate").cpu().numpy()
+        c = pdf.xfxQ2(pids, x, q2, prec=prec, domain="clamp").cpu().numpy()
+        np.testing.assert_array_equal(e[inside], c[inside])
+        assert np.all(np.isnan(e[:3]))
+        assert np.all(np.isfinite(e[3:]))
+    assert pdf.domain_errors() == 2 * 3 * 2          # only the NaN inputs, both modes, 2 precs
+    # Q instead of Q^2
+    eq = pdf.xfxQ(pids, x, np.sqrt(q2), domain="extrapolate").cpu().numpy()
+    ora = oracle.xfx_extrapolated(grid, pids, x, np.sqrt(q2) ** 2)
+    assert err(grid, eq, ora, pids, x, q2) <= 1e-12
+
+
+def test_caller_values_and_other_calls(pdf, grid, torch):
+    from paper_2012_08221_amd.binding import PdfxError
+    pids = [21, 1, -2]
+    x, q2 = outside_points(grid, 5000, 2, 2.0)
+    vals = torch.as_tensor(grid.xf, device="cuda")
+    for prec, dt in (("f64", torch.float64), ("f32s", torch.float32)):
+        a = pdf.xfxQ2(pids, x, q2, prec=prec, domain="extrapolate").cpu().numpy()
+        b = pdf.xfxQ2(pids, x, q2, prec=prec, domain="extrapolate",
+                      values=vals.to(dt).contiguous()).cpu().numpy()
+        np.testing.assert_array_equal(a, b)
+    with pytest.raises(PdfxError, match="EXTRAPOLATE"):
+        from paper_2012_08221_amd import binding as B
+        g = torch.zeros((len(x), 3), dtype=torch.float64, device="cuda")
+        xd = torch.as_tensor(x, device="cuda")
+        qd = torch.as_tensor(q2, device="cuda")
+        B.pdfx_eval_xfx_backward(pdf.handle, None, B.PDFX_F64, np.array(pids, dtype=np.int32),
+                                 xd.data_ptr(), qd.data_ptr(), len(x), g.data_ptr(), None,
+                                 None, None, B.PDFX_DOMAIN_EXTRAPOLATE,
+                                 torch.cuda.current_stream().cuda_stream)
