@@ -1028,7 +1028,7 @@ static int set_build_classes(pdfx_set *s, const pdfx_grid_desc *members, int n_m
         md[m].aq = g->aq.dev();
         md[m].nx = g->ax.n;
         md[m].nq = g->aq.n;
-        md[m].split_rows = 0;
+        md[m].split_rows[0] = md[m].split_rows[1] = 0;
         for (int p = 0; p < 2; ++p) {
             const bool f32 = p == PDFX_F32S;
             int nb = set_node_bytes(g->ax.n, g->aq.n, g->ax.nbuckets, g->aq.nbuckets, f32);
@@ -1036,9 +1036,23 @@ static int set_build_classes(pdfx_set *s, const pdfx_grid_desc *members, int n_m
             for (int c = 0; c < 3; ++c)
                 if (kSetClassWidth[c] == nb)
                     cls = c;
-            if (cls < 0 && !f32) {
-                md[m].split_rows = set_split_rows(g->ax.n, g->aq.n, g->ax.nbuckets, g->aq.nbuckets);
-                if (md[m].split_rows > 0) {
+            // Wider nodes split over both slabs before narrower nodes in one
+            // (fewer stages): 16-byte nodes over both, then 8-byte nodes over
+            // both when even 8-byte nodes do not fit one slab (FP64) or only
+            // 4-byte ones do (FP32).
+            const int nbx = g->ax.nbuckets, nbq = g->aq.nbuckets;
+            if (nb != 16) {
+                const int r16 = set_split_rows(g->ax.n, g->aq.n, nbx, nbq, 16);
+                if (r16 > 0) {
+                    md[m].split_rows[p] = r16;
+                    nb = 16;
+                    cls = 4;
+                }
+            }
+            if (cls < 0 || (f32 && nb == 4)) {
+                const int r8 = set_split_rows(g->ax.n, g->aq.n, nbx, nbq, 8);
+                if (r8 > 0) {
+                    md[m].split_rows[p] = r8;
                     nb = 8;
                     cls = 3;
                 }
@@ -1306,7 +1320,7 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
         for (int c = 0; c < kSetClasses; ++c) {
             if (s->cls_ids[prec][c].empty())
                 continue;
-            if ((e = launch_set_dma(d[c], f32, kSetClassWidth[c], c == 3, ls, s->cus,
+            if ((e = launch_set_dma(d[c], f32, kSetClassWidth[c], kSetClassSplit[c], ls, s->cus,
                                     (hipStream_t)stream)) != hipSuccess)
                 return fail_hip(e, "set launch");
         }

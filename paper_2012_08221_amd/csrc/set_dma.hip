@@ -79,9 +79,10 @@ __device__ __forceinline__ void weights_g<float>(const AxisDev &ax, int i, doubl
     fwd::fold<float>(t, r[2], r[3], r[4], r[5], r[6], r[7], w);
 }
 
-// SPLIT (FP64, 8-byte nodes): the member's group slab is too large for one
-// LDS slab; its rows [0, split_rows) go to slab0 and the rest to slab1, so a
-// stage holds one group in both slabs, copied while no stencil runs.
+// SPLIT: the member's group slab (8- or 16-byte nodes) is too large for one
+// LDS slab; its rows [0, split_rows) go to slab0 and the rest to
+// slab1, so a stage holds one group in both slabs, copied while no stencil
+// runs.
 template <typename V, int NB, int BLOCK, int PPT, bool SPLIT>
 __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
 {
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
         const uint4 *gsrc = reinterpret_cast<const uint4 *>(md.gvals[prec]);
         const size_t gstride = (size_t)md.gstride[prec] * NB / 16;   // chunks per group
         // split layout: rows below r_split in slab0, the others in slab1
-        const int r_split = SPLIT ? md.split_rows : nx;
+        const int r_split = SPLIT ? md.split_rows[prec] : nx;
         const int chunks0 = SPLIT ? r_split * nq * NB / 16 : chunks;   // r_split * nq is even
         const int chunks1 = SPLIT ? chunks - chunks0 : 0;
         auto load_group = [&](int grp) {
@@ -317,14 +318,14 @@ hipError_t launch_typed(const SetDmaArgs &a, LaunchShape ls, int cus, hipStream_
 
 }  // namespace
 
-int set_split_rows(int nx, int nq, int nbx, int nbq)
+int set_split_rows(int nx, int nq, int nbx, int nbq, int nb)
 {
     if (nx < 4 || nq < 4 || nx + nq > kSetKnots || nbx + nbq > kSetSeeds)
         return 0;
-    int r = kSetSlabBytes / (nq * 8);
-    if ((r * nq) % 2)
+    int r = kSetSlabBytes / (nq * nb);
+    if ((r * nq * nb) % 16)
         --r;   // slab0 ends on a 16-byte chunk
-    if (r < 1 || r >= nx || (nx - r) * nq * 8 > kSetSlabBytes)
+    if (r < 1 || r >= nx || (nx - r) * nq * nb > kSetSlabBytes)
         return 0;
     return r;
 }
@@ -356,8 +357,15 @@ bool set_dma_shape_supported(LaunchShape ls)
 hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, bool split, LaunchShape ls,
                           int cus, hipStream_t s)
 {
-    if (split)
-        return !f32 && nb == 8 ? launch_typed<double, 8, true>(a, ls, cus, s) : hipErrorInvalidValue;
+    if (split) {
+        if (nb == 8)
+            return f32 ? launch_typed<float, 8, true>(a, ls, cus, s)
+                       : launch_typed<double, 8, true>(a, ls, cus, s);
+        if (nb == 16)
+            return f32 ? launch_typed<float, 16, true>(a, ls, cus, s)
+                       : launch_typed<double, 16, true>(a, ls, cus, s);
+        return hipErrorInvalidValue;
+    }
     if (f32) {
         if (nb == 16)
             return launch_typed<float, 16>(a, ls, cus, s);

@@ -11,10 +11,11 @@ constexpr int kSetSlabBytes = 78016;
 constexpr int kSetKnots = 320;
 constexpr int kSetSeeds = 1280;
 
-// Classes of the double-buffered set kernel by node bytes; the last is the
-// FP64 class whose slab is split over both LDS slabs.
-constexpr int kSetClasses = 4;
-constexpr int kSetClassWidth[kSetClasses] = {16, 8, 4, 8};
+// Classes of the double-buffered set kernel by node bytes; the last two are
+// the classes whose slab is split over both LDS slabs (8- and 16-byte nodes).
+constexpr int kSetClasses = 5;
+constexpr int kSetClassWidth[kSetClasses] = {16, 8, 4, 8, 16};
+constexpr bool kSetClassSplit[kSetClasses] = {false, false, false, true, true};
 
 // One member as the double-buffered set kernel sees it.
 struct SetMemberDev {
@@ -23,7 +24,7 @@ struct SetMemberDev {
     int gstride[2];         // nodes per group, per precision (node bytes * gstride % 16 == 0)
     int nb[2];              // node bytes per precision (16, 8 or 4); 0: not in a class
     int nx, nq;
-    int split_rows;         // FP64 split class: rows held in the first slab (else 0)
+    int split_rows[2];      // per precision, split classes: rows held in the first slab
 };
 
 struct SetDmaArgs {
@@ -77,12 +78,12 @@ __device__ __forceinline__ void stage_sync_g(uint4 *dst, const void *src, int n,
 // bucket seeds in a precision (16, 8 or 4), or 0 if it does not fit.
 int set_node_bytes(int nx, int nq, int nbx, int nby, bool f32);
 
-// For an FP64 member too large for set_node_bytes: the rows of its 8-byte
-// group slab held in the first LDS slab when the slab is split over both (the
-// rest fitting the second), or 0 if it does not fit that way either.
-int set_split_rows(int nx, int nq, int nbx, int nbq);
+// The rows of a member's group slab of nb-byte nodes held in the first
+// LDS slab when the slab is split over both (the rest fitting the second), or
+// 0 if it does not fit that way.
+int set_split_rows(int nx, int nq, int nbx, int nbq, int nb);
 
-// Launches the class kernel of node width nb (split: the FP64 split class)
+// Launches the class kernel of node width nb (split: an FP64 split class)
 // over args' work list.
 hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, bool split, LaunchShape ls,
                           int cus, hipStream_t s);
