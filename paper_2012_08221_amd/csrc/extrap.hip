@@ -11,7 +11,9 @@
 // The forward kernels run in clamp mode first; this pass then rewrites only
 // the rows of points outside the grid.  Such points are expected to be few,
 // so each is evaluated straight from the bordered per-parton slabs in global
-// memory, one thread per point, with a plain binary search for its bins.
+// memory, one thread per point: the edge knots' indices come from the host,
+// the inside coordinate's bin and weights are found once per point, and each
+// column then needs 4-tap sums along knot lines (or knot values at corners).
 #include "extrap_internal.h"
 #include "xfx_fwd_impl.h"
 
@@ -21,26 +23,27 @@ namespace {
 
 constexpr int kExtrapBlock = 256;
 
-// Largest i in [0, n-2] with k[i] <= v (v inside [k[0], k[n-1]]); a value on a
-// repeated knot takes the upper copy, as in the forward kernels.
-__device__ __forceinline__ int find_bin(const double *k, int n, double v)
+// Bin of v inside the axis: largest i in [0, n-2] with k[i] <= v (a value on
+// a repeated knot takes the upper copy), started from the bucket seed.
+__device__ __forceinline__ int seeded_bin(const AxisDev &ax, double v, double lnv)
 {
-    int lo = 0, hi = n - 2;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (k[mid] <= v)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
+    const double fb = (lnv - ax.ln_lo) * ax.inv_hb;
+    const int b = fb <= 0.0 ? 0 : (fb >= (double)(ax.nbuckets - 1) ? ax.nbuckets - 1 : (int)fb);
+    int i = ax.seed[b];
+    while (i < ax.n - 2 && ax.knots[i + 1] <= v)
+        ++i;
+    while (i > 0 && ax.knots[i] > v)
+        --i;
+    return i;
 }
 
-// Weights of the window of bin i at v.  On a knot they are exactly one-hot:
-// the edge values the continuation starts from are then the data along that
-// knot line, and an edge value that the data make 0 (x f at x = 1) is 0, not
-// a rounding residue that would pick the other branch of the continuation.
-__device__ __forceinline__ void weights64(const AxisDev &ax, int i, double v, double w[4])
+// Weights of the window of bin i at v.  On a knot they are exactly one-hot,
+// as everywhere in this pass: the edge values the continuation starts from
+// are the data along a knot line, and an edge value that the data make 0
+// (x f at x = 1) is 0, not a rounding residue that would pick the other
+// branch of the continuation.
+__device__ __forceinline__ void weights64(const AxisDev &ax, int i, double v, double lnv,
+                                          double w[4])
 {
     if (ax.knots[i] == v || ax.knots[i + 1] == v) {
         const int hot = ax.knots[i] == v ? 1 : 2;
@@ -49,31 +52,8 @@ __device__ __forceinline__ void weights64(const AxisDev &ax, int i, double v, do
         return;
     }
     const IntervalRec<double> r = ax.rec64[i];
-    const double t = (log(v) - r.z) * r.inv_d;
+    const double t = (lnv - r.z) * r.inv_d;
     fwd::fold<double>(t, r.pl, r.plql, r.ql, r.qr, r.qrpr, r.pr, w);
-}
-
-// Interpolated x f of grid row `row` at a point inside the grid, from the
-// bordered slab (zero border one knot wide), in FP64.
-template <typename V>
-__device__ double eval_inside(const ExtrapArgs &a, int row, double xv, double qv)
-{
-    const int ix = find_bin(a.ax.knots, a.nx, xv);
-    const int kq = find_bin(a.aq.knots, a.nq, qv);
-    double wx[4], wq[4];
-    weights64(a.ax, ix, xv, wx);
-    weights64(a.aq, kq, qv, wq);
-    const V *s = reinterpret_cast<const V *>(a.vals) + (size_t)row * a.slab_elems;
-    const int ld = a.nq + 2;
-    double acc = 0.0;
-    for (int j = 0; j < 4; ++j) {
-        const V *r = s + (size_t)(ix + j) * ld + kq;   // bordered row ix-1+j+1, column kq-1+1
-        double rr = 0.0;
-        for (int k = 0; k < 4; ++k)
-            rr = fma(wq[k], (double)r[k], rr);
-        acc = fma(wx[j], rr, acc);
-    }
-    return acc;
 }
 
 __device__ __forceinline__ double cont(double fe, double fn, double u)
@@ -88,7 +68,7 @@ template <typename V>
 __global__ __launch_bounds__(kExtrapBlock) void extrap_kernel(const ExtrapArgs a)
 {
     V *out = reinterpret_cast<V *>(a.out);
-    const double *kx = a.ax.knots, *kq = a.aq.knots;
+    const int ld = a.nq + 2;   // bordered slab: knot (i, k) at (i + 1) * ld + k + 1
     for (int64_t p = (int64_t)blockIdx.x * kExtrapBlock + threadIdx.x; p < a.n;
          p += (int64_t)gridDim.x * kExtrapBlock) {
         const double xv = a.x[p];
@@ -102,25 +82,57 @@ __global__ __launch_bounds__(kExtrapBlock) void extrap_kernel(const ExtrapArgs a
         if (!xo && !qo)
             continue;
         const bool xl = xv < a.ax.lo, ql = qv < a.aq.lo;
-        const double xe = xl ? kx[0] : kx[a.nx - 1], xn = xl ? kx[1] : kx[a.nx - 2];
-        const double qe = ql ? kq[0] : kq[a.nq - 1], qn = ql ? kq[1] : kq[a.nq - 2];
-        const double ux = xo ? log(xv / xe) / log(xn / xe) : 0.0;
-        const double uq = qo ? log(qv / qe) / log(qn / qe) : 0.0;
+        // edge knot e and next knot n of each outside axis (knot indices, the
+        // tie rule applied), the continuation coordinate u
+        const int ie = xl ? a.kx[0] : a.kx[2], in = xl ? a.kx[1] : a.kx[3];
+        const int ce = ql ? a.kq[0] : a.kq[2], cn = ql ? a.kq[1] : a.kq[3];
+        const double ux = xo ? log(xv / a.ax.knots[ie]) / log(a.ax.knots[in] / a.ax.knots[ie]) : 0.0;
+        const double uq = qo ? log(qv / a.aq.knots[ce]) / log(a.aq.knots[cn] / a.aq.knots[ce]) : 0.0;
+        // the coordinate inside, if any: its bin and weights, once per point
+        double w[4] = {0.0, 0.0, 0.0, 0.0};
+        int bin = 0;
+        if (!qo) {
+            const double lq = log(qv);
+            bin = seeded_bin(a.aq, qv, lq);
+            weights64(a.aq, bin, qv, lq, w);
+        } else if (!xo) {
+            const double lx = log(xv);
+            bin = seeded_bin(a.ax, xv, lx);
+            weights64(a.ax, bin, xv, lx, w);
+        }
         V *o = out + p * a.n_req;
+#pragma unroll 4
         for (int r = 0; r < a.n_req; ++r) {
             const int row = a.row[r];
             double v = 0.0;
             if (row >= 0) {
+                const V *s = reinterpret_cast<const V *>(a.vals) + (size_t)row * a.slab_elems;
                 if (xo && !qo) {
-                    v = cont(eval_inside<V>(a, row, xe, qv), eval_inside<V>(a, row, xn, qv), ux);
+                    // along Q^2 on the x knot lines ie and in (window columns bin .. bin+3)
+                    const V *re = s + (size_t)(ie + 1) * ld + bin;
+                    const V *rn = s + (size_t)(in + 1) * ld + bin;
+                    double fe = 0.0, fn = 0.0;
+                    for (int k = 0; k < 4; ++k) {
+                        fe = fma(w[k], (double)re[k], fe);
+                        fn = fma(w[k], (double)rn[k], fn);
+                    }
+                    v = cont(fe, fn, ux);
                 } else if (qo && !xo) {
-                    v = cont(eval_inside<V>(a, row, xv, qe), eval_inside<V>(a, row, xv, qn), uq);
+                    // along x on the Q^2 knot lines ce and cn (window rows bin .. bin+3)
+                    double fe = 0.0, fn = 0.0;
+                    for (int j = 0; j < 4; ++j) {
+                        const V *rj = s + (size_t)(bin + j) * ld;
+                        fe = fma(w[j], (double)rj[ce + 1], fe);
+                        fn = fma(w[j], (double)rj[cn + 1], fn);
+                    }
+                    v = cont(fe, fn, uq);
                 } else {
-                    const double ce = cont(eval_inside<V>(a, row, xe, qe),
-                                           eval_inside<V>(a, row, xn, qe), ux);
-                    const double cn = cont(eval_inside<V>(a, row, xe, qn),
-                                           eval_inside<V>(a, row, xn, qn), ux);
-                    v = cont(ce, cn, uq);
+                    // corners: knot values; x first, then Q^2
+                    const double a_e = cont((double)s[(size_t)(ie + 1) * ld + ce + 1],
+                                            (double)s[(size_t)(in + 1) * ld + ce + 1], ux);
+                    const double a_n = cont((double)s[(size_t)(ie + 1) * ld + cn + 1],
+                                            (double)s[(size_t)(in + 1) * ld + cn + 1], ux);
+                    v = cont(a_e, a_n, uq);
                 }
             }
             o[r] = (V)v;

@@ -11,6 +11,8 @@ struct ExtrapArgs {
     int nx, nq, slab_elems;
     int n_req;
     int row[kMaxReq];          // grid row of output column r, or -1 (absent parton: 0)
+    int kx[4];                 // x knot indices: low edge, next inward, high edge, next inward
+    int kq[4];                 // Q^2 knot indices, the same (a repeated knot: its upper copy)
     const double *x, *q;       // [n]; q is Q^2, or Q if q_is_q
     int q_is_q;
     void *out;                 // [n][n_req]; only rows of points outside the grid are written

@@ -339,6 +339,26 @@ static int eval_xfx_common(const pdfx_grid *g, const void *xf_dev, int prec, con
     e.n_req = n_req;
     for (int r = 0; r < n_req; ++r)
         e.row[r] = g->row_of(pids[r]);
+    // knot index evaluated at a knot value: the bin rule of the forward
+    // kernels (largest i <= n-2 with k[i] <= v; a repeated knot's upper copy),
+    // then the knot itself
+    auto knot_at = [](const std::vector<double> &k, double v) {
+        const int n = (int)k.size();
+        int i = 0;
+        while (i < n - 2 && k[i + 1] <= v)
+            ++i;
+        return k[i] == v ? i : i + 1;
+    };
+    const std::vector<double> &kx = g->ax.knots, &kq = g->aq.knots;
+    const int nxk = (int)kx.size(), nqk = (int)kq.size();
+    e.kx[0] = knot_at(kx, kx[0]);
+    e.kx[1] = knot_at(kx, kx[1]);
+    e.kx[2] = knot_at(kx, kx[nxk - 1]);
+    e.kx[3] = knot_at(kx, kx[nxk - 2]);
+    e.kq[0] = knot_at(kq, kq[0]);
+    e.kq[1] = knot_at(kq, kq[1]);
+    e.kq[2] = knot_at(kq, kq[nqk - 1]);
+    e.kq[3] = knot_at(kq, kq[nqk - 2]);
     e.x = x;
     e.q = q;
     e.q_is_q = q_is_q;
