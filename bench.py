@@ -377,18 +377,25 @@ def main():
                 B.pdfx_eval_lumi(pdf.handle, None, code, pa, pb, None, x1.data_ptr(),
                                  x2.data_ptr(), None, 172.5 ** 2, nl, L.data_ptr(), S.data_ptr(),
                                  0, stream.cuda_stream)
+            tune = {}
+            for shape in ((512, 1), (512, 2), (256, 2)):
+                pdf.set_lumi_launch(prec, *shape)
+                tune[shape] = timed(run_sum, 3)
+            best = min(tune, key=tune.get)
+            pdf.set_lumi_launch(prec, *best)
             ms_s = timed(run_sum, 5)
             ms_b = timed(run_both, 5)
             vb = 8 if prec == "f64" else 4
             lres[prec] = {"sum_ms": ms_s, "sum_points_per_s": nl / (ms_s * 1e-3),
                           "sum_hbm_gbs_algorithmic": nl * (16 + vb) / ms_s / 1e6,
                           "pairs_and_sum_ms": ms_b,
-                          "pairs_and_sum_hbm_gbs_algorithmic": nl * (16 + 5 * vb) / ms_b / 1e6}
+                          "pairs_and_sum_hbm_gbs_algorithmic": nl * (16 + 5 * vb) / ms_b / 1e6,
+                          "launch_shape": list(best),
+                          "shape_sum_ms": {"%dx%d" % k: v for k, v in tune.items()}}
             log("lumi %s: sum %.3f ms, pairs+sum %.3f ms" % (prec, ms_s, ms_b))
             del S, L
         variants["lumi"] = {"n_points": nl, "pairs": [list(t) for t in zip(pa, pb)],
-                            "q2": 172.5 ** 2, "launch_shape": list(pdf.lumi_launch("f64")),
-                            **lres}
+                            "q2": 172.5 ** 2, **lres}
         if args.only == "lumi":
             print(json.dumps({"only": "lumi", **variants["lumi"]}))
             return

@@ -88,12 +88,7 @@ __global__ __launch_bounds__(BLOCK) void lumi_kernel(const LumiArgs a)
 
     // Domain rule of the forward evaluation applied to x1, x2 and Q^2
     // together; logs, bins, weights and windows of both points.
-    auto locate = [&](int64_t p, LumiPoint<V> &st) {
-        double x1 = load_point(a.x1, p, a.n);
-        double x2 = load_point(a.x2, p, a.n);
-        double q2 = q2_fixed;
-        if (q2_arr)
-            q2 = load_point(a.q2, p, a.n);
+    auto locate = [&](int64_t p, double x1, double x2, double q2, LumiPoint<V> &st) {
         const bool nan_in = (x1 != x1) || (x2 != x2) || (q2 != q2);
         const bool inside = x1 >= a.ax.lo && x1 <= a.ax.hi && x2 >= a.ax.lo && x2 <= a.ax.hi &&
                             q2 >= a.aq.lo && q2 <= a.aq.hi;
@@ -143,16 +138,34 @@ __global__ __launch_bounds__(BLOCK) void lumi_kernel(const LumiArgs a)
         }
     };
 
+    // The coordinates of a tile are requested one tile ahead, so that their
+    // memory latency passes during the previous tile's stages.
+    double cx1[PPT], cx2[PPT], cq2[PPT];
+    auto load_coords = [&](int64_t t) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int64_t p = t * tile_pts + tid + (int64_t)j * BLOCK;
+            cx1[j] = load_point(a.x1, p, a.n);
+            cx2[j] = load_point(a.x2, p, a.n);
+            cq2[j] = q2_fixed;
+            if (q2_arr)
+                cq2[j] = load_point(a.q2, p, a.n);
+        }
+    };
+    load_coords(blockIdx.x);
+
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t t0 = tile * tile_pts;
         const bool more = tile + gridDim.x < ntiles;
         LumiPoint<V> pt[PPT];
 #pragma unroll
         for (int j = 0; j < PPT; ++j)
-            locate(t0 + tid + (int64_t)j * BLOCK, pt[j]);
+            locate(t0 + tid + (int64_t)j * BLOCK, cx1[j], cx2[j], cq2[j], pt[j]);
 
         fwd::wait_vm();
         __syncthreads();   // the tile's first slab has landed
+        if (more)
+            load_coords(tile + gridDim.x);   // waited for with the first stage's copy
 
         V r1[PPT][NSG], r2[PPT][NSG];
 #pragma unroll
