@@ -21,6 +21,11 @@
  *    only enqueues work on it and returns; nothing is copied to or from the
  *    host on the eval path.
  *  - A failed call leaves every handle valid and enqueues nothing.
+ *  - A grid (or set) owns scratch memory that its calls share: repacked
+ *    caller values, the adjoint and integrand-gradient workspaces and the
+ *    domain counter.  Calls on one handle are ordered by being on one stream;
+ *    calls that may run at the same time on different streams need different
+ *    handles.
  *  - PDG ids: 21 and 0 both mean the gluon; a pid absent from the grid
  *    evaluates to 0; output columns follow the request order.
  *  - Points outside the grid: PDFX_DOMAIN_NAN writes NaN for every column of

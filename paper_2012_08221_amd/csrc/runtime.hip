@@ -323,12 +323,12 @@ static int eval_xfx_common(const pdfx_grid *g, const void *xf_dev, int prec, con
                               extrap ? PDFX_DOMAIN_CLAMP : domain_mode, &a);
     if (rc != PDFX_OK || n_pts == 0)
         return rc;
+    if (extrap && ((uintptr_t)out & (prec == PDFX_F64 ? 7 : 3)))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
     a.q_is_q = q_is_q;
     rc = run_xfx(g, a, xf_dev, prec, (hipStream_t)stream);
     if (rc != PDFX_OK || !extrap)
         return rc;
-    if ((uintptr_t)out & (prec == PDFX_F64 ? 7 : 3))
-        return fail(PDFX_EINVAL, "misaligned device pointer");
     ExtrapArgs e{};
     e.ax = g->ax.dev();
     e.aq = g->aq.dev();
