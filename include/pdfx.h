@@ -26,6 +26,12 @@
  *    domain counter.  Calls on one handle are ordered by being on one stream;
  *    calls that may run at the same time on different streams need different
  *    handles.
+ *  - Eval calls allocate nothing, except that pdfx_eval_xfx_backward and
+ *    pdfx_eval_dy_backward grow their handle's workspace (a synchronous device
+ *    allocation) the first time they see a larger n; a call sequence meant
+ *    for HIP graph capture is run once at full size before capturing it.
+ *    No call records a memset: scratch that must start at zero is cleared by
+ *    kernels on the call's stream.
  *  - PDG ids: 21 and 0 both mean the gluon; a pid absent from the grid
  *    evaluates to 0; output columns follow the request order.
  *  - Points outside the grid: PDFX_DOMAIN_NAN writes NaN for every column of
