@@ -48,7 +48,7 @@ class FormatError(ValueError):
 
 def _floats(line: str, what: str, path: str) -> np.ndarray:
     try:
-        return np.array([float(t) for t in line.split()], dtype=np.float64)
+        return np.array(line.split(), dtype=np.float64)
     except ValueError as e:
         raise FormatError("%s: bad %s line: %s" % (path, what, e)) from None
 
@@ -111,9 +111,9 @@ def read_member(path: str, info: dict | None = None) -> MemberGrid:
         if len(rows) != xb.size * qb.size:
             raise FormatError("%s: block %d has %d value lines, expected %d x %d"
                               % (path, b, len(rows), xb.size, qb.size))
-        vals = np.array([_floats(r, "value", path) for r in rows])
-        if vals.ndim != 2 or vals.shape[1] != pb.size:
+        if any(len(r.split()) != pb.size for r in rows):
             raise FormatError("%s: block %d: every value line needs %d entries" % (path, b, pb.size))
+        vals = _floats(" ".join(rows), "value", path).reshape(len(rows), pb.size)
         if x is None:
             x, pids = xb, pb
         else:
