@@ -64,23 +64,32 @@ __device__ __forceinline__ double cont(double fe, double fn, double u)
     return fe + u * (fn - fe);
 }
 
+// True if point p is outside the grid (and no coordinate is NaN: such a
+// point keeps the forward pass's NaN).
+__device__ __forceinline__ bool outside(const ExtrapArgs &a, int64_t p)
+{
+    const double xv = a.x[p];
+    double qv = a.q[p];
+    if (a.q_is_q)
+        qv = qv * qv;
+    if (xv != xv || qv != qv)
+        return false;
+    return xv < a.ax.lo || xv > a.ax.hi || qv < a.aq.lo || qv > a.aq.hi;
+}
+
+// The continuation of one point outside the grid, every output column.
 template <typename V>
-__global__ __launch_bounds__(kExtrapBlock) void extrap_kernel(const ExtrapArgs a)
+__device__ void continue_point(const ExtrapArgs &a, int64_t p)
 {
     V *out = reinterpret_cast<V *>(a.out);
     const int ld = a.nq + 2;   // bordered slab: knot (i, k) at (i + 1) * ld + k + 1
-    for (int64_t p = (int64_t)blockIdx.x * kExtrapBlock + threadIdx.x; p < a.n;
-         p += (int64_t)gridDim.x * kExtrapBlock) {
+    {
         const double xv = a.x[p];
         double qv = a.q[p];
         if (a.q_is_q)
             qv = qv * qv;
-        if (xv != xv || qv != qv)
-            continue;   // NaN input: NaN from the forward pass
         const bool xo = xv < a.ax.lo || xv > a.ax.hi;
         const bool qo = qv < a.aq.lo || qv > a.aq.hi;
-        if (!xo && !qo)
-            continue;
         const bool xl = xv < a.ax.lo, ql = qv < a.aq.lo;
         // edge knot e and next knot n of each outside axis (knot indices, the
         // tie rule applied), the continuation coordinate u
@@ -140,11 +149,40 @@ __global__ __launch_bounds__(kExtrapBlock) void extrap_kernel(const ExtrapArgs a
     }
 }
 
+// Each workgroup takes chunks of kExtrapChunk points: it lists the chunk's
+// outside points in LDS, then continues them with every lane busy (outside
+// points are few and scattered, so most waves would otherwise run the long
+// path for one lane).
+constexpr int kExtrapChunk = 4096;
+
+template <typename V>
+__global__ __launch_bounds__(kExtrapBlock) void extrap_kernel(const ExtrapArgs a)
+{
+    __shared__ int list[kExtrapChunk];
+    __shared__ int count;
+    for (int64_t c0 = (int64_t)blockIdx.x * kExtrapChunk; c0 < a.n;
+         c0 += (int64_t)gridDim.x * kExtrapChunk) {
+        if (threadIdx.x == 0)
+            count = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < kExtrapChunk; i += kExtrapBlock) {
+            const int64_t p = c0 + i;
+            if (p < a.n && outside(a, p))
+                list[atomicAdd(&count, 1)] = i;
+        }
+        __syncthreads();
+        const int n_out = count;
+        for (int k = threadIdx.x; k < n_out; k += kExtrapBlock)
+            continue_point<V>(a, c0 + list[k]);
+        __syncthreads();   // the list is read before the next chunk refills it
+    }
+}
+
 }  // namespace
 
 hipError_t launch_extrap(const ExtrapArgs &a, bool f32, int cus, hipStream_t s)
 {
-    int64_t grid = (a.n + kExtrapBlock - 1) / kExtrapBlock;
+    int64_t grid = (a.n + kExtrapChunk - 1) / kExtrapChunk;
     if (grid > (int64_t)cus * 8)
         grid = (int64_t)cus * 8;
     if (grid < 1)
