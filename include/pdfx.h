@@ -207,7 +207,12 @@ int pdfx_autotune_set(pdfx_set *s, int prec, int32_t n_req, int64_t n_pts, const
 
 /* Current launch shape of a grid: workgroup size and points per thread. */
 int pdfx_get_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
-/* Forces a launch shape (must be one of the compiled ones). */
+/* Forces a launch shape (must be one of the compiled ones): ppt > 0 holds
+ * results in registers ((256, 2), (256, 4), (512, 1), (512, 2), (1024, 1),
+ * and for PDFX_F32S also (512, 4), which only the double-buffered kernel has:
+ * other FP32 kernels run it as (512, 2)); ppt < 0 stores results as they are
+ * produced ((256, -2), (256, -4), (256, -8), (512, -1), (512, -2), (512, -4),
+ * (1024, -1), (1024, -2)). */
 int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 
 /* Launch shape of the double-buffered integrand kernel (pdfx_eval_dy on

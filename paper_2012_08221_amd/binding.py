@@ -34,6 +34,8 @@ PDFX_MAX_REQ = 64
 LAUNCH_SHAPES = ((256, 2), (256, 4), (512, 1), (512, 2), (1024, 1),
                  (256, -2), (256, -4), (256, -8), (512, -1), (512, -2), (512, -4), (1024, -1),
                  (1024, -2))
+# Shapes compiled for the FP32-stencil precision only (double-buffered kernel).
+LAUNCH_SHAPES_F32 = ((512, 4),)
 
 # Every function the header declares, in header order.
 EXPORTS = (

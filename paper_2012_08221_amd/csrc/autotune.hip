@@ -177,8 +177,10 @@ extern "C" int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pt
     key << arch_name() << "|cu" << g->cus << "|xfx|" << g->nf << "x" << g->ax.n << "x" << g->aq.n
         << "s" << g->n_sub << "|p" << prec << "|r" << n_req << "|n2^" << size_class(n_pts);
     CacheEntry ce = cache_lookup(cache_path, key.str());
-    if (ce.found && launch_shape_supported(LaunchShape{ce.block, ce.ppt})) {
-        g->shape[prec] = LaunchShape{ce.block, ce.ppt};
+    const LaunchShape cached{ce.block, ce.ppt};
+    if (ce.found && (launch_shape_supported(cached) ||
+                     (prec == PDFX_F32S && launch_shape_f32_only(cached)))) {
+        g->shape[prec] = cached;
         return PDFX_OK;
     }
     const int64_t n = n_pts < (1LL << 23) ? n_pts : (1LL << 23);
@@ -192,8 +194,12 @@ extern "C" int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pt
     const LaunchShape keep = g->shape[prec];
     double best = 1e30;
     LaunchShape best_ls = keep;
-    for (int i = 0; i < n_launch_shapes(); ++i) {
-        const LaunchShape ls = launch_shape_at(i);
+    std::vector<LaunchShape> cand;
+    for (int i = 0; i < n_launch_shapes(); ++i)
+        cand.push_back(launch_shape_at(i));
+    if (prec == PDFX_F32S)
+        cand.push_back(LaunchShape{512, 4});
+    for (const LaunchShape ls : cand) {
         g->shape[prec] = ls;
         g->reset_occupancy(prec);
         const double ms = time_min(

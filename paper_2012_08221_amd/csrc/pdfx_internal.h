@@ -226,7 +226,7 @@ hipError_t xfx_dma_occupancy_f32s(LaunchShape ls, int *blocks_per_cu);
 // True if the double-buffered kernel is compiled for ls and its static LDS
 // holds two node slabs and the search tables of an nx x nq grid with nbx and
 // nbq bucket seeds.
-bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq);
+bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq, bool f32 = false);
 hipError_t launch_alphas(const AlphasArgs &a, bool f32, hipStream_t s);
 hipError_t launch_repack(const RepackArgs &a, bool f32, hipStream_t s);
 hipError_t launch_backward(const BwdArgs &a, bool f32, void *grad_xf, double *grad_x,
@@ -252,6 +252,9 @@ bool set_shape_supported(LaunchShape ls);
 int n_set_shapes();
 LaunchShape set_shape_at(int i);
 bool launch_shape_supported(LaunchShape ls);
+// Shapes only the FP32 double-buffered kernel has (other FP32 kernels run
+// them as (512, 2)).
+bool launch_shape_f32_only(LaunchShape ls);
 int n_launch_shapes();
 LaunchShape launch_shape_at(int i);
 

@@ -462,8 +462,9 @@ int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
     if (prec != PDFX_F64 && prec != PDFX_F32S)
         return fail(PDFX_EINVAL, "unknown precision %d", prec);
     LaunchShape ls{block, ppt};
-    if (!launch_shape_supported(ls))
-        return fail(PDFX_EINVAL, "launch shape (%d, %d) not compiled", block, ppt);
+    if (!launch_shape_supported(ls) && !(prec == PDFX_F32S && launch_shape_f32_only(ls)))
+        return fail(PDFX_EINVAL, "launch shape (%d, %d) not compiled for this precision", block,
+                    ppt);
     g->shape[prec] = ls;
     return PDFX_OK;
 }
@@ -821,10 +822,10 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
 {
     hipError_t e;
     const bool f32 = prec == PDFX_F32S;
-    const LaunchShape ls = g->shape[prec];
+    LaunchShape ls = g->shape[prec];
     const bool staged = ls.ppt > 0 && plan_stages(a, f32 ? 4 : 2);
     if (staged && g->dma_grid && (uintptr_t)a.out % 16 == 0 &&
-        dma_supported(ls, a.nx, a.nq, a.ax.nbuckets, a.aq.nbuckets)) {
+        dma_supported(ls, a.nx, a.nq, a.ax.nbuckets, a.aq.nbuckets, f32)) {
         a.gvals = g->dvals[prec].ptr;
         a.gstride = a.nx * a.nq;
         if (xf_dev) {
@@ -833,12 +834,14 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
                 return fail_hip(e, "repack launch");
             a.gvals = g->scratch_dvals[prec].ptr;
         }
-        const int maxb = g->max_blocks(prec, a, 2);
+        const int maxb = g->max_blocks(prec, a, 2, ls);
         e = f32 ? launch_xfx_dma_f32s(a, ls, maxb, s) : launch_xfx_dma_f64(a, ls, maxb, s);
         if (e != hipSuccess)
             return fail_hip(e, "xfx launch");
         return PDFX_OK;
     }
+    if (launch_shape_f32_only(ls))
+        ls = LaunchShape{512, 2};   // the other kernels' nearest shape
     bool grouped = staged && grp_shape_supported(ls, a.nx, a.nq);
     if (grouped) {
         XfxArgs probe = a;
@@ -853,7 +856,7 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
                 return fail_hip(e, "repack launch");
             a.gvals = g->scratch_gvals[prec].ptr;
         }
-        const int maxb = g->max_blocks(prec, a, 1);
+        const int maxb = g->max_blocks(prec, a, 1, ls);
         e = f32 ? launch_xfx_grp_f32s(a, ls, maxb, s) : launch_xfx_grp_f64(a, ls, maxb, s);
         if (e != hipSuccess)
             return fail_hip(e, "xfx launch");
@@ -865,7 +868,7 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
             return fail_hip(e, "repack launch");
         a.vals = g->scratch_vals[prec].ptr;
     }
-    const int maxb = g->max_blocks(prec, a, 0);
+    const int maxb = g->max_blocks(prec, a, 0, ls);
     e = f32 ? launch_xfx_f32s(a, ls, maxb, s) : launch_xfx_f64(a, ls, maxb, s);
     if (e != hipSuccess)
         return fail_hip(e, "xfx launch");
@@ -876,9 +879,9 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
 
 // Resident workgroups of the current launch shape over the whole device
 // (cached per precision and kernel; the persistent kernels never launch more).
-int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a, int kernel) const
+int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a, int kernel,
+                          pdfx::LaunchShape ls) const
 {
-    const pdfx::LaunchShape ls = shape[prec];
     if (occ_shape[prec][kernel].block == ls.block && occ_shape[prec][kernel].ppt == ls.ppt &&
         occ_blocks[prec][kernel] > 0)
         return occ_blocks[prec][kernel];

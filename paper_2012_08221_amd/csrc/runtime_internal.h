@@ -78,7 +78,7 @@ struct pdfx_grid {
     mutable pdfx::LaunchShape occ_shape[2][3] = {};
     mutable int occ_blocks[2][3] = {};
     int row_of(int pid) const;
-    int max_blocks(int prec, const pdfx::XfxArgs &a, int kernel) const;
+    int max_blocks(int prec, const pdfx::XfxArgs &a, int kernel, pdfx::LaunchShape ls) const;
     void reset_occupancy(int prec) const { occ_blocks[prec][0] = occ_blocks[prec][1] = occ_blocks[prec][2] = 0; }
 };
 

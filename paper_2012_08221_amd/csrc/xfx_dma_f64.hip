@@ -13,11 +13,13 @@ hipError_t xfx_dma_occupancy_f64(LaunchShape ls, int *blocks_per_cu)
     return fwd::dma_occupancy_typed<double>(ls, blocks_per_cu);
 }
 
-bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq)
+bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq, bool f32)
 {
     if (nx < 4 || nq < 4 || nx * nq > fwd::kDmaNodes || nx + nq > fwd::kDmaKnots ||
         nbx + nbq > fwd::kDmaSeeds)
         return false;
+    if (f32 && ls.block == fwd::kDmaShapeF32.block && ls.ppt == fwd::kDmaShapeF32.ppt)
+        return true;
     for (const auto &k : fwd::kDmaShapes)
         if (k.block == ls.block && k.ppt == ls.ppt)
             return true;

@@ -312,8 +312,11 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
     wait_vm();
 }
 
-// Compiled launch shapes (block, points per thread) of the double-buffered kernel.
+// Compiled launch shapes (block, points per thread) of the double-buffered kernel;
+// FP32 also has (512, 4): its results take half the registers of FP64's, so
+// twice the points per tile fit and the per-tile work is shared by more points.
 constexpr LaunchShape kDmaShapes[] = {{256, 2}, {256, 4}, {512, 1}, {512, 2}, {1024, 1}};
+constexpr LaunchShape kDmaShapeF32 = {512, 4};
 
 template <typename V, typename Call>
 hipError_t with_dma_variant(LaunchShape ls, Call call)
@@ -323,6 +326,10 @@ hipError_t with_dma_variant(LaunchShape ls, Call call)
     if (ls.block == 512 && ls.ppt == 1) return call(xfx_dma_kernel<V, 512, 1>, 512, 1);
     if (ls.block == 512 && ls.ppt == 2) return call(xfx_dma_kernel<V, 512, 2>, 512, 2);
     if (ls.block == 1024 && ls.ppt == 1) return call(xfx_dma_kernel<V, 1024, 1>, 1024, 1);
+    if constexpr (sizeof(V) == 4) {
+        if (ls.block == kDmaShapeF32.block && ls.ppt == kDmaShapeF32.ppt)
+            return call(xfx_dma_kernel<V, 512, 4>, 512, 4);
+    }
     return hipErrorInvalidValue;
 }
 

@@ -21,6 +21,8 @@ bool launch_shape_supported(LaunchShape ls)
     return false;
 }
 
+bool launch_shape_f32_only(LaunchShape ls) { return ls.block == 512 && ls.ppt == 4; }
+
 int n_launch_shapes() { return (int)(sizeof(fwd::kShapes) / sizeof(fwd::kShapes[0])); }
 LaunchShape launch_shape_at(int i) { return fwd::kShapes[i]; }
 

@@ -70,7 +70,11 @@ def test_all_launch_shapes_agree(pdf0, torch, prec):
     keep = pdf0.launch(prec)
     ref = None
     try:
-        shapes = list(__import__('paper_2012_08221_amd.binding', fromlist=['x']).LAUNCH_SHAPES)
+        B = __import__('paper_2012_08221_amd.binding', fromlist=['x'])
+        shapes = list(B.LAUNCH_SHAPES) + (list(B.LAUNCH_SHAPES_F32) if prec == "f32s" else [])
+        if prec == "f64":
+            with pytest.raises(B.PdfxError, match="not compiled"):
+                pdf0.set_launch(prec, *B.LAUNCH_SHAPES_F32[0])
         for blk, ppt in shapes:
             pdf0.set_launch(prec, blk, ppt)
             out = pdf0.xfxQ2(g.pids, xd, qd, prec=prec).cpu().numpy()
@@ -95,7 +99,8 @@ def test_unaligned_out_matches_aligned(pdf0, torch, api, prec):
     n = x.shape[0]
     keep = pdf0.launch(prec)
     try:
-        for blk, ppt in ((256, 2), (512, 1), (512, 2), (1024, 1)):
+        shapes = [(256, 2), (512, 1), (512, 2), (1024, 1)] + ([(512, 4)] if prec == "f32s" else [])
+        for blk, ppt in shapes:   # (512, 4) unaligned runs as (512, 2) in the grouped kernel
             pdf0.set_launch(prec, blk, ppt)
             ref = pdf0.xfxQ2(g.pids, xd, qd, prec=prec).cpu().numpy()
             buf = torch.full((n * 11 + 1,), -7.0, dtype=api.prec_dtype(prec), device="cuda")
