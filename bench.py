@@ -330,7 +330,7 @@ def main():
                                u2.data_ptr(), csize, wl.DY_XMIN, wl.SQRT_S_DY ** 2,
                                outd.data_ptr(), sums.data_ptr(), stream.cuda_stream)
             tune = {}
-            for shape in ((512, 1), (512, 2), (256, 2)):
+            for shape in ((512, 1), (512, 2), (256, 2)) + (((512, 4),) if prec == "f32s" else ()):
                 pdf.set_dy_launch(prec, *shape)
                 tune[shape] = timed(fwd_one, 3)
             best = min(tune, key=tune.get)
@@ -378,7 +378,7 @@ def main():
                                  x2.data_ptr(), None, 172.5 ** 2, nl, L.data_ptr(), S.data_ptr(),
                                  0, stream.cuda_stream)
             tune = {}
-            for shape in ((512, 1), (512, 2), (256, 2)):
+            for shape in ((512, 1), (512, 2), (256, 2)) + (((512, 4),) if prec == "f32s" else ()):
                 pdf.set_lumi_launch(prec, *shape)
                 tune[shape] = timed(run_sum, 3)
             best = min(tune, key=tune.get)

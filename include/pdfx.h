@@ -218,7 +218,8 @@ int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 /* Launch shape of the double-buffered integrand kernel (pdfx_eval_dy on
  * grids with the 11 partons in the standard order that fit its LDS):
  * workgroup size and points per thread; compiled: (512, 1), (512, 2),
- * (256, 2).  Other grids use a fixed single-slab kernel. */
+ * (256, 2), and (512, 4) for PDFX_F32S.  Other grids use a fixed single-slab
+ * kernel. */
 int pdfx_get_dy_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
 int pdfx_set_dy_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 
@@ -248,7 +249,7 @@ int pdfx_eval_lumi(const pdfx_grid *g, const void *xf_dev, int prec, int32_t n_p
                    int64_t n, void *out_pair, void *out_sum, int domain_mode, void *stream);
 
 /* Launch shape of the luminosity kernel per precision (default (512, 2));
- * compiled: (512, 1), (512, 2), (256, 2). */
+ * compiled: (512, 1), (512, 2), (256, 2), and (512, 4) for PDFX_F32S. */
 int pdfx_get_lumi_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
 int pdfx_set_lumi_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 

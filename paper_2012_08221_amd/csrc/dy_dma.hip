@@ -229,6 +229,9 @@ __global__ __launch_bounds__(BLOCK) void dy_dma_kernel(const DyArgs a)
             }
         }
 #pragma unroll
+        for (int j = NS; j < PPT; ++j)
+            locate_next(j);   // more points per thread than stages
+#pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const V I = (V)a.L2 * cur[j].as * lum[j];
             const int64_t p = t0 + tid + (int64_t)j * BLOCK;
@@ -289,6 +292,10 @@ hipError_t dy_dma_typed(const DyArgs &a, LaunchShape ls, int cus, hipStream_t s,
         return go(dy_dma_kernel<V, 512, 2>, 512, 2);
     if (ls.block == 256 && ls.ppt == 2)
         return go(dy_dma_kernel<V, 256, 2>, 256, 2);
+    if constexpr (sizeof(V) == 4) {
+        if (ls.block == 512 && ls.ppt == 4)
+            return go(dy_dma_kernel<V, 512, 4>, 512, 4);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -398,9 +405,10 @@ hipError_t launch_dy_pair_adjoint(const DyArgs &a0, bool f32, int cus, hipStream
     return hipGetLastError();
 }
 
-bool dy_shape_supported(LaunchShape ls)
+bool dy_shape_supported(LaunchShape ls, bool f32)
 {
-    return (ls.block == 512 && (ls.ppt == 1 || ls.ppt == 2)) || (ls.block == 256 && ls.ppt == 2);
+    return (ls.block == 512 && (ls.ppt == 1 || ls.ppt == 2)) || (ls.block == 256 && ls.ppt == 2) ||
+           (f32 && ls.block == 512 && ls.ppt == 4);
 }
 
 bool dy_dma_supported(int nx, int nq, int na, int nbx, int nbq)

@@ -268,6 +268,10 @@ hipError_t launch_typed(const LumiArgs &a, LaunchShape ls, int cus, hipStream_t 
         return go(lumi_kernel<V, 512, 2>, 512, 2);
     if (ls.block == 256 && ls.ppt == 2)
         return go(lumi_kernel<V, 256, 2>, 256, 2);
+    if constexpr (sizeof(V) == 4) {
+        if (ls.block == 512 && ls.ppt == 4)
+            return go(lumi_kernel<V, 512, 4>, 512, 4);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -279,8 +283,10 @@ bool lumi_supported(int nx, int nq, int nbx, int nbq)
            nbx + nbq <= kDmaSeeds;
 }
 
-bool lumi_shape_supported(LaunchShape ls)
+bool lumi_shape_supported(LaunchShape ls, bool f32)
 {
+    if (f32 && ls.block == 512 && ls.ppt == 4)
+        return true;
     for (const auto &k : kLumiShapes)
         if (k.block == ls.block && k.ppt == ls.ppt)
             return true;

@@ -34,7 +34,7 @@ struct LumiArgs {
 };
 
 bool lumi_supported(int nx, int nq, int nbx, int nbq);
-bool lumi_shape_supported(LaunchShape ls);
+bool lumi_shape_supported(LaunchShape ls, bool f32);
 hipError_t launch_lumi(const LumiArgs &a, bool f32, LaunchShape ls, int cus, hipStream_t s);
 
 }  // namespace pdfx

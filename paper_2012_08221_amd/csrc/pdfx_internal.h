@@ -239,7 +239,7 @@ size_t dy_lds_layout(DyArgs &a, bool f32, bool *db);
 // knots and nbx, nbq bucket seeds (the standard 11-parton order is checked
 // by the caller).
 bool dy_dma_supported(int nx, int nq, int na, int nbx, int nbq);
-bool dy_shape_supported(LaunchShape ls);
+bool dy_shape_supported(LaunchShape ls, bool f32);
 // Knot-gradient pass of the integrand backward by quark-antiquark pairs
 // (standard parton order; a.gvals/gstride: borderless group slabs; the state
 // arrays and the zeroed FP64 accumulator as for launch_dy_backward).

@@ -489,7 +489,7 @@ int pdfx_set_dy_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
     if (prec != PDFX_F64 && prec != PDFX_F32S)
         return fail(PDFX_EINVAL, "unknown precision %d", prec);
     LaunchShape ls{block, ppt};
-    if (!dy_shape_supported(ls))
+    if (!dy_shape_supported(ls, prec == PDFX_F32S))
         return fail(PDFX_EINVAL, "integrand launch shape (%d, %d) not compiled", block, ppt);
     g->dy_shape[prec] = ls;
     return PDFX_OK;
@@ -515,7 +515,7 @@ int pdfx_set_lumi_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
     if (prec != PDFX_F64 && prec != PDFX_F32S)
         return fail(PDFX_EINVAL, "unknown precision %d", prec);
     LaunchShape ls{block, ppt};
-    if (!lumi_shape_supported(ls))
+    if (!lumi_shape_supported(ls, prec == PDFX_F32S))
         return fail(PDFX_EINVAL, "luminosity launch shape (%d, %d) not compiled", block, ppt);
     g->lumi_shape[prec] = ls;
     return PDFX_OK;
