@@ -240,7 +240,10 @@ extern "C" int pdfx_autotune_set(pdfx_set *s, int prec, int32_t n_req, int64_t n
         << s->max_nx << "x" << s->max_nq << "|p" << prec << "|r" << n_req << "|n2^"
         << size_class(n_pts);
     CacheEntry ce = cache_lookup(cache_path, key.str());
-    if (ce.found && set_shape_supported(LaunchShape{ce.block, ce.ppt}) && ce.tpi >= 1) {
+    const LaunchShape cached_set{ce.block, ce.ppt};
+    if (ce.found && ce.tpi >= 1 &&
+        (set_shape_supported(cached_set) ||
+         (prec == PDFX_F32S && launch_shape_f32_only(cached_set)))) {
         s->shape[prec] = LaunchShape{ce.block, ce.ppt};
         s->tiles_per_item[prec] = ce.tpi;
         return PDFX_OK;
@@ -258,9 +261,14 @@ extern "C" int pdfx_autotune_set(pdfx_set *s, int prec, int32_t n_req, int64_t n
     double best = 1e30;
     LaunchShape best_ls = s->shape[prec];
     int best_tpi = s->tiles_per_item[prec];
-    for (int i = 0; i < n_set_shapes(); ++i) {
+    std::vector<LaunchShape> cand;
+    for (int i = 0; i < n_set_shapes(); ++i)
+        cand.push_back(set_shape_at(i));
+    if (prec == PDFX_F32S)
+        cand.push_back(LaunchShape{512, 4});
+    for (const LaunchShape ls : cand) {
         for (int tpi : {1, 2, 4, 8}) {
-            s->shape[prec] = set_shape_at(i);
+            s->shape[prec] = ls;
             s->tiles_per_item[prec] = tpi;
             const double ms = time_min(
                 [&](hipStream_t st) {
@@ -271,7 +279,7 @@ extern "C" int pdfx_autotune_set(pdfx_set *s, int prec, int32_t n_req, int64_t n
                 (hipStream_t)0, 2);
             if (ms < best) {
                 best = ms;
-                best_ls = set_shape_at(i);
+                best_ls = ls;
                 best_tpi = tpi;
             }
         }

@@ -1288,7 +1288,7 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
     // result slots.  The other members (or all, otherwise) go through the
     // single-slab kernel.
     SetDmaArgs d[kSetClasses];
-    bool dma = set_dma_shape_supported(ls) && (uintptr_t)out % 16 == 0 &&
+    bool dma = set_dma_shape_supported(ls, f32) && (uintptr_t)out % 16 == 0 &&
                (n_pts * n_req * (f32 ? 4 : 8)) % 16 == 0;
     for (int c = 0; c < kSetClasses && dma; ++c) {
         if (s->cls_ids[prec][c].empty())
@@ -1352,7 +1352,14 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
         a.mem_ids = (const int *)s->ids_dev[prec][kSetClasses].ptr;
         a.n_items = (int)(s->rest_ids[prec].size() * ipm);
     }
-    e = launch_set(a, f32, ls, lds, s->cus, (hipStream_t)stream);
+    // the single-slab kernel runs the FP32-only class shape as (512, 2): tiles
+    // of half the points, twice as many per work item (same points per item)
+    LaunchShape ls_set = ls;
+    if (launch_shape_f32_only(ls)) {
+        ls_set = LaunchShape{512, 2};
+        a.tiles_per_item *= 2;
+    }
+    e = launch_set(a, f32, ls_set, lds, s->cus, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail_hip(e, "set launch");
     return PDFX_OK;

@@ -313,6 +313,10 @@ hipError_t launch_typed(const SetDmaArgs &a, LaunchShape ls, int cus, hipStream_
         return go(set_dma_kernel<V, NB, 512, 2, SPLIT>, 512);
     if (ls.block == 256 && ls.ppt == 2)
         return go(set_dma_kernel<V, NB, 256, 2, SPLIT>, 256);
+    if constexpr (sizeof(V) == 4) {
+        if (ls.block == 512 && ls.ppt == 4)
+            return go(set_dma_kernel<V, NB, 512, 4, SPLIT>, 512);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -346,8 +350,10 @@ int set_node_bytes(int nx, int nq, int nbx, int nbq, bool f32)
     return 0;
 }
 
-bool set_dma_shape_supported(LaunchShape ls)
+bool set_dma_shape_supported(LaunchShape ls, bool f32)
 {
+    if (f32 && ls.block == 512 && ls.ppt == 4)
+        return true;
     for (const auto &k : kSetDmaShapes)
         if (k.block == ls.block && k.ppt == ls.ppt)
             return true;

@@ -87,6 +87,7 @@ int set_split_rows(int nx, int nq, int nbx, int nbq, int nb);
 // over args' work list.
 hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, bool split, LaunchShape ls,
                           int cus, hipStream_t s);
-bool set_dma_shape_supported(LaunchShape ls);
+// (512, 4) is compiled for FP32 only.
+bool set_dma_shape_supported(LaunchShape ls, bool f32);
 
 }  // namespace pdfx

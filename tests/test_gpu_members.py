@@ -96,6 +96,42 @@ def test_shapes_and_work_split_agree(pset, members, tmp_path):
         assert e <= tol
 
 
+def test_f32_class_shape_and_fallback_agree(pset, members, torch, tmp_path):
+    """FP32 sets: the class kernels at (512, 2) and at the FP32-only (512, 4),
+    with two work splits, and an unaligned output (every member through the
+    single-slab kernel, which runs (512, 4) as (512, 2) with twice the tiles
+    per work item) all give the same bits."""
+    from paper_2012_08221_amd import api
+    from paper_2012_08221_amd import binding as B
+    n = 30_000                                   # 16-byte aligned member blocks
+    x, q2 = wl.queries(11, n)
+    pids = [21, 2, -3]
+    cache = tmp_path / "tune32.jsonl"
+    pset.autotune("f32s", n_req=3, n_pts=n, cache_path=str(cache))
+    key = cache.read_text().strip().splitlines()[-1].split('"key": "')[1].split('"')[0]
+    ref = None
+    try:
+        for blk, ppt in ((512, 2), (512, 4)):
+            for tpi in (1, 3):
+                with open(cache, "a") as fh:
+                    fh.write('{"key": "%s", "block": %d, "ppt": %d, "tpi": %d, "ms": 0}\n'
+                             % (key, blk, ppt, tpi))
+                B.pdfx_autotune_set(pset.handle, B.PDFX_F32S, 3, n, str(cache))
+                out = pset.xfxQ2(pids, x, q2, prec="f32s").cpu().numpy()
+                if ref is None:
+                    ref = out
+                np.testing.assert_array_equal(out, ref)
+        buf = torch.empty(101 * n * 3 + 1, dtype=torch.float32, device="cuda")
+        un = buf[1:].view(101, n, 3)
+        pset.xfxQ2(pids, x, q2, prec="f32s", out=un)
+        np.testing.assert_array_equal(un.cpu().numpy(), ref)
+    finally:
+        pset.autotune("f32s", n_req=3, n_pts=n)
+    for k in (0, 50, 100):
+        e, tol = check_member(members[k], ref[k], x, q2, pids, "f32s")
+        assert e <= tol, (k, e)
+
+
 def test_one_member_set_matches_single_grid(torch, members):
     from paper_2012_08221_amd import api
     m = members[3]
