@@ -33,9 +33,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-# LDS: 128 B/clk per compute unit (a lane-consecutive ds_read_b128 stream
-# reaches 125 B/clk), 256 compute units, 2.4 GHz
-LDS_PEAK_GBS = 128 * 256 * 2.4
 N_PTS = 10_000_000
 METRIC = "PDF evals/sec (points×flavours) FP32 vs FP64 at stated rel. error; fwd+bwd/s"
 
@@ -81,20 +78,22 @@ def forward_kernel_sources():
 
 
 def forward_kernel_name(prec, launch):
-    """Kernel that pdfx_eval_xfx runs for the bench grid (it fits the
-    double-buffered kernel) with launch shape (block, ppt)."""
+    """Kernel that pdfx_eval_xfx_alphas runs for the bench grid (it fits the
+    double-buffered kernel, and its alpha_s knots are its Q^2 knots, so x f and
+    alpha_s come from one pass) with launch shape (block, ppt)."""
     v = "double" if prec == "f64" else "float"
     block, ppt = launch
     if ppt > 0:
-        return "xfx_dma_kernel<%s, %d, %d>" % (v, block, ppt)
+        return "xfx_dma_kernel<%s, %d, %d, true>" % (v, block, ppt)
     return "xfx_kernel<%s, %d, %d, PF, DB, 0>" % (v, block, -ppt)
 
 
 def lds_bytes(prec, launch, n, nf, nx, nq):
     """LDS bytes one forward launch moves (double-buffered kernel, ppt > 0):
     stencil reads (16 nodes of 16 B per point and flavour group), global-to-
-    LDS slab copies (one slab per group and tile) and the output rows staged
-    through LDS (written, then read).  None for the per-flavour kernel."""
+    LDS slab copies (one slab per group and tile), the output rows staged
+    through LDS (written, then read) and the four alpha_s values per point.
+    None for the per-flavour kernel."""
     block, ppt = launch
     if ppt <= 0:
         return None
@@ -102,7 +101,7 @@ def lds_bytes(prec, launch, n, nf, nx, nq):
     g = 16 // vb
     stages = (nf + g - 1) // g
     tiles = (n + block * ppt - 1) // (block * ppt)
-    return n * stages * 16 * 16 + tiles * stages * nx * nq * 16 + 2 * n * nf * vb
+    return n * stages * 16 * 16 + tiles * stages * nx * nq * 16 + 2 * n * nf * vb + n * 4 * vb
 
 
 def recorded_traffic(prec, launch):
@@ -163,6 +162,19 @@ def main():
         del a, b
         return n, ms, 2 * n * 8 / ms / 1e6
 
+    def lds_read_gbs():
+        """LDS read rates the device reaches (pdfx_bench_lds_read, 8 workgroups
+        per CU): aligned 16-byte reads, lane-consecutive and at random addresses."""
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        blocks, iters = cus * 8, 4096
+        sink = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+        rates = {}
+        for mode, name in ((0, "measured_stream_gbs"), (1, "measured_random_gbs")):
+            ms = timed(lambda: B.pdfx_bench_lds_read(mode, blocks, iters, sink.data_ptr(),
+                                                     stream.cuda_stream), 5)
+            rates[name] = blocks * 256 * iters * 16 / ms / 1e6
+        return rates
+
     if args.calib_copy:
         n, ms, gbs = copy_gbs()
         print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8,
@@ -199,12 +211,10 @@ def main():
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
                     e0.record(stream)
-                pdf.xfxQ2(pids, x, q2, prec=prec, out=out)
+                pdf.xfx_alphasQ2(pids, x, q2, prec=prec, out=out, as_out=aout)
                 if rec:
                     e1.record(stream)
                     ev.append((e0, e1))
-                if args.only is None:
-                    pdf.alphasQ2(q2, prec=prec, out=aout)
 
             for _ in range(args.warmup):
                 step(False)
@@ -218,7 +228,7 @@ def main():
             torch.cuda.synchronize()
             ms = t0.elapsed_time(t1) / args.steps
             k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-            results[prec] = {"ms": ms, "xfx_ms": k_ms, "out": out,
+            results[prec] = {"ms": ms, "xfx_ms": k_ms, "out": out, "as": aout,
                              "launch": list(pdf.launch(prec))}
             log("%s: %.3f ms per step, xfx kernel %.3f ms" % (prec, ms, k_ms))
         if args.only == "xfx":
@@ -402,7 +412,7 @@ def main():
 
     head = results[args.prec]
     value = n * nf / (head["ms"] * 1e-3)
-    bytes_per_pt = 16 + nf * (8 if args.prec == "f64" else 4)
+    bytes_per_pt = 16 + (nf + 1) * (8 if args.prec == "f64" else 4)   # x, Q^2 in; x f, alpha_s out
     achieved = n * bytes_per_pt / (head["xfx_ms"] * 1e-3) / 1e9
 
     # CPU baseline: the oracle on the host cores over the workload's points
@@ -419,6 +429,7 @@ def main():
         for _ in range(3):
             t0 = time.perf_counter()
             ora = oracle.xfx(grid, pids, x_np[:nc], q2_np[:nc], nthreads=threads)
+            ora_as = oracle.alphas(grid.as_q2, grid.as_val, q2_np[:nc], nthreads=threads)
             walls.append(time.perf_counter() - t0)
         dt = sorted(walls)[1]
         n1 = min(nc, 100_000)
@@ -426,8 +437,8 @@ def main():
         oracle.xfx(grid, pids, x_np[:n1], q2_np[:n1], nthreads=1)
         dt1 = time.perf_counter() - t0
         cpu = {"value": nc * nf / dt, "unit": "pf/s", "cores": threads, "kind": "oracle",
-               "sample": "all %d points x %d flavours of the step, FP64, median of 3: %.2f s wall"
-                         % (nc, nf, dt),
+               "sample": "all %d points x %d flavours and alpha_s of the step, FP64, median "
+                         "of 3: %.2f s wall" % (nc, nf, dt),
                "cpu_model": cpu_model(),
                "one_thread": {"value": n1 * nf / dt1, "unit": "pf/s",
                               "sample": "first %d points, FP64" % n1}}
@@ -453,12 +464,16 @@ def main():
             got = r["out"][:ns].double().cpu().numpy()
             den = np.maximum(np.abs(ora[:ns]), 0.1 * M)
             e = np.abs(got - ora[:ns]) / np.where(den == 0, 1.0, den)
+            got_as = r["as"][:ns].double().cpu().numpy()
             err[prec] = {"max_rel_err_capped": float(e.max()),
+                         "alphas_max_rel_err": float(np.max(np.abs(got_as - ora_as[:ns])
+                                                            / np.abs(ora_as[:ns]))),
                          "per_flavour_max": [float(v) for v in e.max(axis=0)],
                          "points_checked": ns}
 
+    lds_meas = lds_read_gbs() if results else {}
     for prec, r in results.items():
-        bpp = 16 + nf * (8 if prec == "f64" else 4)
+        bpp = 16 + (nf + 1) * (8 if prec == "f64" else 4)
         variants[prec] = {
             "value": n * nf / (r["ms"] * 1e-3), "unit": "pf/s", "ms_per_step": r["ms"],
             "xfx_kernel_ms": r["xfx_ms"], "launch_shape": r["launch"],
@@ -467,10 +482,15 @@ def main():
             **err.get(prec, {})}
         lb = lds_bytes(prec, r["launch"], n, nf, grid.n_x, grid.n_q)
         if lb is not None:
-            variants[prec]["lds"] = {"bytes_per_launch": lb,
-                                     "achieved_gbs": lb / (r["xfx_ms"] * 1e-3) / 1e9,
-                                     "peak_gbs": LDS_PEAK_GBS,
-                                     "frac": lb / (r["xfx_ms"] * 1e-3) / 1e9 / LDS_PEAK_GBS}
+            # LDS ceiling: the rates the device is measured to reach in this
+            # run (pdfx_bench_lds_read), lane-consecutive reads as the peak
+            ach = lb / (r["xfx_ms"] * 1e-3) / 1e9
+            peak = lds_meas["measured_stream_gbs"]
+            variants[prec]["lds"] = {
+                "bytes_per_launch": lb, "achieved_gbs": ach, "peak_gbs": peak,
+                "peak_kind": "measured, lane-consecutive 16-byte LDS reads", "frac": ach / peak,
+                "random_gbs": lds_meas["measured_random_gbs"],
+                "frac_of_random": ach / lds_meas["measured_random_gbs"]}
 
     copy = copy_gbs()[2]
     rec = {

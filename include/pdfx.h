@@ -138,6 +138,24 @@ int pdfx_eval_xfxQ(const pdfx_grid *g, const void *xf_dev, int prec,
 int pdfx_eval_alphas(const pdfx_grid *g, const double *q2, int64_t n, void *out,
                      int prec, int domain_mode, void *stream);
 
+/* x f and alpha_s at the same points in one call, as an integrand needs both
+ * (Sec. 4's examples): the results of pdfx_eval_xfx(g, xf_dev, prec, pids,
+ * n_req, x, q2, n_pts, out, domain_mode, stream) and of pdfx_eval_alphas(g,
+ * q2, n_pts, as_out, prec, domain_mode, stream): x f bit for bit, alpha_s to
+ * rounding (a few ulp), the same NaNs and the same domain counting (a point
+ * with Q^2 outside counts once for each).  as_out:
+ * device [n_pts], FP64 or FP32 per prec.  domain_mode PDFX_DOMAIN_NAN or
+ * PDFX_DOMAIN_CLAMP.  When the alpha_s knots are the grid's Q^2 knots (same
+ * values, same subgrids), alpha_s is formed in the x f pass from the point's
+ * Q^2 weights, one pass over the points instead of two; otherwise the two
+ * passes run one after the other.  PDFX_ENOALPHAS if the grid has no alpha_s
+ * knots; other errors as pdfx_eval_xfx and as_out NULL or misaligned.
+ * Asynchronous on stream. */
+int pdfx_eval_xfx_alphas(const pdfx_grid *g, const void *xf_dev, int prec,
+                         const int32_t *pids, int32_t n_req,
+                         const double *x, const double *q2, int64_t n_pts,
+                         void *out, void *as_out, int domain_mode, void *stream);
+
 /* ---- adjoint (derivative of the Sec. 2.1 map; used for differentiable fits) ----
  * For a scalar L with dL/dout = grad_out ([n_pts][n_req], precision's type):
  *  grad_xf  device [n_flav][n_x][n_q] of the precision's type, ACCUMULATED:
@@ -258,6 +276,18 @@ int pdfx_set_lumi_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 /* Number of out-of-grid points counted since the last call, over all eval
  * calls on g; synchronises the device, then resets the counter. */
 int pdfx_domain_errors(const pdfx_grid *g, int64_t *count);
+
+/* Measurement helper, not part of the method: the device's rate of aligned
+ * 16-byte LDS reads, the ceiling of the stencil kernels (their stencils are
+ * such reads at data-dependent addresses).  Enqueues `blocks` workgroups of
+ * 256 threads; each thread makes `iters` reads from a 64 KB LDS array,
+ * lane-consecutive (mode 0: each wave reads 1 KB in one piece) or at
+ * independent random 16-byte-aligned addresses (mode 1).  LDS bytes read per
+ * call = blocks * 256 * iters * 16; the caller times the call on `stream`.
+ * `sink`: device, blocks * 256 doubles, receives per-thread sums so that the
+ * reads are kept.  PDFX_EINVAL for another mode, blocks or iters <= 0, or a
+ * NULL sink.  Asynchronous on stream. */
+int pdfx_bench_lds_read(int mode, int blocks, int iters, double *sink, void *stream);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char *pdfx_last_error(void);

@@ -95,6 +95,23 @@ class PDF:
     py_xfxQ = xfxQ
     py_xfxQ2 = xfxQ2
 
+    def xfx_alphasQ2(self, pids, x, q2, prec="f64", values=None, domain="nan", out=None,
+                     as_out=None):
+        """x f for each pid and alpha_s at the same points, in one call
+        -> ([n, len(pids)], [n]); x f equal to xfxQ2, alpha_s to alphasQ2 up to rounding."""
+        x = _device_f64(x)
+        q2 = _device_f64(q2, x.device)
+        pids = np.atleast_1d(np.asarray(pids, dtype=np.int32))
+        n = x.numel()
+        if out is None:
+            out = torch.empty((n, pids.shape[0]), dtype=prec_dtype(prec), device=x.device)
+        if as_out is None:
+            as_out = torch.empty(n, dtype=prec_dtype(prec), device=x.device)
+        B.pdfx_eval_xfx_alphas(self.handle, _ptr(values), prec_code(prec), pids, x.data_ptr(),
+                               q2.data_ptr(), n, out.data_ptr(), as_out.data_ptr(),
+                               _DOMAIN[domain], _stream(x.device))
+        return out, as_out
+
     # -- alpha_s --
     def alphasQ2(self, q2, prec="f64", domain="nan", out=None):
         q2 = _device_f64(q2)

@@ -40,12 +40,12 @@ LAUNCH_SHAPES_F32 = ((512, 4),)
 # Every function the header declares, in header order.
 EXPORTS = (
     "pdfx_load_grid", "pdfx_free_grid", "pdfx_grid_shape", "pdfx_eval_xfx", "pdfx_eval_xfxQ",
-    "pdfx_eval_alphas", "pdfx_eval_xfx_backward", "pdfx_load_set", "pdfx_free_set",
+    "pdfx_eval_alphas", "pdfx_eval_xfx_alphas", "pdfx_eval_xfx_backward", "pdfx_load_set", "pdfx_free_set",
     "pdfx_eval_set_xfx", "pdfx_eval_dy", "pdfx_dy_max_blocks", "pdfx_eval_dy_backward",
     "pdfx_autotune", "pdfx_autotune_set", "pdfx_get_launch", "pdfx_set_launch",
     "pdfx_get_dy_launch", "pdfx_set_dy_launch",
     "pdfx_eval_lumi", "pdfx_get_lumi_launch", "pdfx_set_lumi_launch",
-    "pdfx_domain_errors", "pdfx_last_error", "pdfx_version",
+    "pdfx_domain_errors", "pdfx_bench_lds_read", "pdfx_last_error", "pdfx_version",
 )
 
 
@@ -91,6 +91,7 @@ def lib():
             "pdfx_eval_xfx": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, i32, vp], i32),
             "pdfx_eval_xfxQ": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, i32, vp], i32),
             "pdfx_eval_alphas": ([vp, vp, i64, vp, i32, i32, vp], i32),
+            "pdfx_eval_xfx_alphas": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, vp, i32, vp], i32),
             "pdfx_eval_xfx_backward": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, vp, vp, vp, i32,
                                         vp], i32),
             "pdfx_load_set": ([vp, i32, vp], i32),
@@ -110,6 +111,7 @@ def lib():
             "pdfx_get_lumi_launch": ([vp, i32, vp, vp], i32),
             "pdfx_set_lumi_launch": ([vp, i32, i32, i32], i32),
             "pdfx_domain_errors": ([vp, vp], i32),
+            "pdfx_bench_lds_read": ([i32, i32, i32, vp, vp], i32),
             "pdfx_last_error": ([], ctypes.c_char_p),
             "pdfx_version": ([], ctypes.c_char_p),
         }
@@ -182,6 +184,13 @@ def pdfx_eval_xfxQ(h, xf_dev, prec, pids, x_ptr, q_ptr, n_pts, out_ptr, domain_m
     arr, p = _pids(pids)
     return check(lib().pdfx_eval_xfxQ(h, xf_dev, prec, p, arr.shape[0], x_ptr, q_ptr, n_pts,
                                       out_ptr, domain_mode, stream))
+
+
+def pdfx_eval_xfx_alphas(h, xf_dev, prec, pids, x_ptr, q2_ptr, n_pts, out_ptr, as_ptr,
+                         domain_mode, stream):
+    arr, p = _pids(pids)
+    return check(lib().pdfx_eval_xfx_alphas(h, xf_dev, prec, p, arr.shape[0], x_ptr, q2_ptr,
+                                            n_pts, out_ptr, as_ptr, domain_mode, stream))
 
 
 def pdfx_eval_alphas(h, q2_ptr, n, out_ptr, prec, domain_mode, stream):
@@ -294,6 +303,12 @@ def pdfx_grid_shape(h):
     v = [ctypes.c_int32() for _ in range(5)]
     check(lib().pdfx_grid_shape(h, *[ctypes.byref(a) for a in v]))
     return tuple(a.value for a in v)
+
+
+def pdfx_bench_lds_read(mode: int, blocks: int, iters: int, sink_ptr: int, stream: int):
+    """Enqueues the LDS read micro-benchmark (mode 0 lane-consecutive, 1 random);
+    LDS bytes read = blocks * 256 * iters * 16."""
+    check(lib().pdfx_bench_lds_read(mode, blocks, iters, sink_ptr, stream))
 
 
 def pdfx_version() -> str:

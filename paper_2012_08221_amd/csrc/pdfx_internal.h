@@ -96,6 +96,11 @@ struct XfxArgs {
     int dup_src[kMaxReq];         //   column dup_dst[d] repeats column dup_src[d]
     int dup_dst[kMaxReq];
     int out_pass_pts;             // > 0: output rows staged in LDS this many points at a time
+    // alpha_s at the same points (double-buffered kernel only, when the
+    // alpha_s knots are the Q^2 knots): knot values padded with a zero at
+    // each end, and the output [n]; as_out NULL = no alpha_s
+    const void *as_vals;
+    void *as_out;
 };
 
 struct BwdArgs {
@@ -227,6 +232,8 @@ hipError_t xfx_dma_occupancy_f32s(LaunchShape ls, int *blocks_per_cu);
 // holds two node slabs and the search tables of an nx x nq grid with nbx and
 // nbq bucket seeds.
 bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq, bool f32 = false);
+// The alpha_s values of a Q^2 axis of nq knots fit the kernel's LDS after the knots.
+bool dma_alphas_fit(int nx, int nq, bool f32);
 hipError_t launch_alphas(const AlphasArgs &a, bool f32, hipStream_t s);
 hipError_t launch_repack(const RepackArgs &a, bool f32, hipStream_t s);
 hipError_t launch_backward(const BwdArgs &a, bool f32, void *grad_xf, double *grad_x,

@@ -391,6 +391,36 @@ int pdfx_eval_xfxQ(const pdfx_grid *g, const void *xf_dev, int prec, const int32
     return eval_xfx_common(g, xf_dev, prec, pids, n_req, x, q, n_pts, out, domain_mode, stream, 1);
 }
 
+int pdfx_eval_xfx_alphas(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
+                         int32_t n_req, const double *x, const double *q2, int64_t n_pts,
+                         void *out, void *as_out, int domain_mode, void *stream)
+{
+    clear_error();
+    if (!g)
+        return fail(PDFX_EINVAL, "grid is NULL");
+    if (!g->has_alphas)
+        return fail(PDFX_ENOALPHAS, "grid has no alpha_s knots");
+    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP)
+        return fail(PDFX_EINVAL, "domain mode %d: alpha_s takes NAN or CLAMP", domain_mode);
+    XfxArgs a;
+    int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q2, n_pts, out, domain_mode, &a);
+    if (rc != PDFX_OK || n_pts == 0)
+        return rc;
+    if (!as_out)
+        return fail(PDFX_EINVAL, "as_out is NULL");
+    if ((uintptr_t)as_out & (prec == PDFX_F64 ? 7 : 3))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    bool as_done = false;
+    if (g->alphas_on_q) {
+        a.as_vals = prec == PDFX_F64 ? g->as_vals64.ptr : g->as_vals32.ptr;   // padded
+        a.as_out = as_out;
+    }
+    rc = run_xfx(g, a, xf_dev, prec, (hipStream_t)stream, &as_done);
+    if (rc != PDFX_OK || as_done)
+        return rc;
+    return pdfx_eval_alphas(g, q2, n_pts, as_out, prec, domain_mode, stream);
+}
+
 int pdfx_eval_alphas(const pdfx_grid *g, const double *q2, int64_t n, void *out, int prec,
                      int domain_mode, void *stream)
 {
@@ -690,6 +720,15 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
         if ((e = g->as_vals32.upload(p32.data(), p32.size() * sizeof(float))) != hipSuccess)
             return fail_hip(e, "upload alpha_s");
         g->has_alphas = true;
+        const AxisHost &aa = g->aa, &aq = g->aq;
+        g->alphas_on_q = aa.n == aq.n && aa.nbuckets == aq.nbuckets && aa.ln_lo == aq.ln_lo &&
+                         aa.inv_hb == aq.inv_hb && aa.knots == aq.knots && aa.seed == aq.seed &&
+                         aa.rec64.size() == aq.rec64.size() &&
+                         std::memcmp(aa.rec64.data(), aq.rec64.data(),
+                                     aa.rec64.size() * sizeof(aa.rec64[0])) == 0 &&
+                         aa.rec32.size() == aq.rec32.size() &&
+                         std::memcmp(aa.rec32.data(), aq.rec32.data(),
+                                     aa.rec32.size() * sizeof(aa.rec32[0])) == 0;
     }
     if ((e = g->dom_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess)
         return fail_hip(e, "allocate domain counter");
@@ -818,10 +857,13 @@ static bool plan_stages(XfxArgs &a, int G)
 // request's groups fit them: the double-buffered one when the grid fits its
 // LDS and `out` is 16-byte aligned, else the single-buffer one when its slab
 // fits; everything else uses the per-flavour kernel.
-int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s)
+int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s,
+            bool *as_done)
 {
     hipError_t e;
     const bool f32 = prec == PDFX_F32S;
+    if (as_done)
+        *as_done = false;
     LaunchShape ls = g->shape[prec];
     const bool staged = ls.ppt > 0 && plan_stages(a, f32 ? 4 : 2);
     if (staged && g->dma_grid && (uintptr_t)a.out % 16 == 0 &&
@@ -834,12 +876,20 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
                 return fail_hip(e, "repack launch");
             a.gvals = g->scratch_dvals[prec].ptr;
         }
+        if (a.as_out && !dma_alphas_fit(a.nx, a.nq, f32)) {
+            a.as_out = nullptr;
+            a.as_vals = nullptr;
+        }
         const int maxb = g->max_blocks(prec, a, 2, ls);
         e = f32 ? launch_xfx_dma_f32s(a, ls, maxb, s) : launch_xfx_dma_f64(a, ls, maxb, s);
         if (e != hipSuccess)
             return fail_hip(e, "xfx launch");
+        if (as_done)
+            *as_done = a.as_out != nullptr;
         return PDFX_OK;
     }
+    a.as_out = nullptr;
+    a.as_vals = nullptr;
     if (launch_shape_f32_only(ls))
         ls = LaunchShape{512, 2};   // the other kernels' nearest shape
     bool grouped = staged && grp_shape_supported(ls, a.nx, a.nq);

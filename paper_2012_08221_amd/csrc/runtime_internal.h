@@ -55,6 +55,9 @@ struct pdfx_grid {
     int cus = 256;
     bool has_values = false;
     bool has_alphas = false;
+    // alpha_s axis identical to the Q^2 axis (knots, subgrid split, tables):
+    // alpha_s can then use the Q^2 weights of the forward kernel
+    bool alphas_on_q = false;
     std::vector<int32_t> pids;
     std::vector<int32_t> q_off;
     pdfx::AxisHost ax, aq, aa;
@@ -88,7 +91,10 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d);
 int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
                      int32_t n_req, const double *x, const double *q, int64_t n_pts, void *out,
                      int domain_mode, XfxArgs *a);
-int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s);
+// Runs the forward pass.  With a.as_out set, the double-buffered kernel also
+// writes alpha_s; *as_done tells whether it did (the other kernels do not).
+int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s,
+            bool *as_done = nullptr);
 
 }  // namespace pdfx
 

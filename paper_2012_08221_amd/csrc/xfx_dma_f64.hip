@@ -13,6 +13,12 @@ hipError_t xfx_dma_occupancy_f64(LaunchShape ls, int *blocks_per_cu)
     return fwd::dma_occupancy_typed<double>(ls, blocks_per_cu);
 }
 
+bool dma_alphas_fit(int nx, int nq, bool f32)
+{
+    const int vb = f32 ? 4 : 8;
+    return (nx + nq) * 8 + ((nq + 2) * vb + 7) / 8 * 8 <= fwd::kDmaKnots * 8;
+}
+
 bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq, bool f32)
 {
     if (nx < 4 || nq < 4 || nx * nq > fwd::kDmaNodes || nx + nq > fwd::kDmaKnots ||

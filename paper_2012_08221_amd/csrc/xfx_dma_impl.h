@@ -92,6 +92,35 @@ __device__ __forceinline__ void dma_slab(uint4 *dst, const uint4 *src, int nodes
                 (__attribute__((address_space(3))) void *)(dst + b), 16, 0, 0);
 }
 
+// Domain rule of the forward kernels with the Q^2 coordinate judged on its
+// own as well, for alpha_s at the same point: returns whether x f is defined
+// (as domain() does) and sets q_ok to whether alpha_s is (Q^2 inside, or
+// clamped and not NaN).  Each out-of-range coordinate is replaced on its own,
+// so a valid Q^2 keeps its value when only x is outside.
+__device__ __forceinline__ bool domain_xq(const XfxArgs &a, double &xv, double &qv, bool &q_ok)
+{
+    const bool x_in = xv >= a.ax.lo && xv <= a.ax.hi;   // false for NaN
+    const bool q_in = qv >= a.aq.lo && qv <= a.aq.hi;
+    if (x_in && q_in) {
+        q_ok = true;
+        return true;
+    }
+    const bool x_nan = xv != xv;
+    const bool q_nan = qv != qv;
+    if (a.domain_mode == 1) {
+        xv = x_nan ? a.ax.lo : fmin(fmax(xv, a.ax.lo), a.ax.hi);
+        qv = q_nan ? a.aq.lo : fmin(fmax(qv, a.aq.lo), a.aq.hi);
+        q_ok = !q_nan;
+        return !x_nan && !q_nan;
+    }
+    if (!x_in)
+        xv = a.ax.lo;
+    if (!q_in)
+        qv = a.aq.lo;
+    q_ok = q_in;
+    return false;
+}
+
 // Wait until this wave's outstanding vector-memory operations (global-to-LDS
 // copies included) are complete; other waves read what it copied after the
 // barrier that follows.
@@ -130,7 +159,11 @@ __device__ __forceinline__ void dma_stage(const uint4 *slab, const int base[PPT]
     }
 }
 
-template <typename V, int BLOCK, int PPT>
+// AS: alpha_s at the same points as well.  The alpha_s knots are the Q^2
+// knots, so alpha_s is the Q^2 weights of the point applied to the alpha_s
+// values of the same 4-knot window; the values sit in LDS after the knots
+// (dma_alphas_fit), and alpha_s is written as soon as the point is located.
+template <typename V, int BLOCK, int PPT, bool AS = false>
 __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
 {
     constexpr int G = 16 / (int)sizeof(V);
@@ -161,6 +194,11 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
     copy_words<BLOCK>(reinterpret_cast<char *>(seeds), a.ax.seed, a.ax.nbuckets * 2);
     copy_words<BLOCK>(reinterpret_cast<char *>(seeds + a.ax.nbuckets), a.aq.seed,
                       a.aq.nbuckets * 2);
+    // alpha_s values, padded (a zero before knot 0), after the knots
+    const V *asv = reinterpret_cast<const V *>(knots + nx + nq) + 1;
+    if constexpr (AS)
+        copy_words<BLOCK>(reinterpret_cast<char *>(knots + nx + nq), a.as_vals,
+                          ((nq + 2) * (int)sizeof(V) + 7) / 8 * 8);
     __syncthreads();
     LAxis lx, lq;
     lx.k = knots;
@@ -181,15 +219,31 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
     auto locate = [&](double xv, double qv, int64_t p, V (&ox)[4], V (&oq)[4], int &ob, bool &ook) {
         if (a.q_is_q)
             qv = qv * qv;
-        ook = domain(a, xv, qv);
+        bool q_ok = true;
+        if constexpr (AS)
+            ook = domain_xq(a, xv, qv, q_ok);
+        else
+            ook = domain(a, xv, qv);
         count_flagged(p < a.n && !ook, a.dom_count);
+        if constexpr (AS)
+            count_flagged(p < a.n && !q_ok, a.dom_count);
         const double lnx = log(xv);
         const double lnq = log(qv);
         const int ix = lbin(lx, xv, lnx);
         const int kq = lbin(lq, qv, lnq);
         weights_gmem<V>(a.ax, ix, lnx, ox);
         weights_gmem<V>(a.aq, kq, lnq, oq);
-        ob = window(ix, nx, ox) * nq + window(kq, nq, oq);
+        const int wq0 = window(kq, nq, oq);
+        ob = window(ix, nx, ox) * nq + wq0;
+        if constexpr (AS) {
+            const V *av = asv + wq0;
+            V s = oq[0] * av[0];
+            s = fma(oq[1], av[1], s);
+            s = fma(oq[2], av[2], s);
+            s = fma(oq[3], av[3], s);
+            if (p < a.n)
+                reinterpret_cast<V *>(a.as_out)[p] = q_ok ? s : quiet_nan<V>();
+        }
     };
 
     // Point state of the current tile, and of the next tile (located during
@@ -318,26 +372,26 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
 constexpr LaunchShape kDmaShapes[] = {{256, 2}, {256, 4}, {512, 1}, {512, 2}, {1024, 1}};
 constexpr LaunchShape kDmaShapeF32 = {512, 4};
 
-template <typename V, typename Call>
+template <typename V, bool AS, typename Call>
 hipError_t with_dma_variant(LaunchShape ls, Call call)
 {
-    if (ls.block == 256 && ls.ppt == 2) return call(xfx_dma_kernel<V, 256, 2>, 256, 2);
-    if (ls.block == 256 && ls.ppt == 4) return call(xfx_dma_kernel<V, 256, 4>, 256, 4);
-    if (ls.block == 512 && ls.ppt == 1) return call(xfx_dma_kernel<V, 512, 1>, 512, 1);
-    if (ls.block == 512 && ls.ppt == 2) return call(xfx_dma_kernel<V, 512, 2>, 512, 2);
-    if (ls.block == 1024 && ls.ppt == 1) return call(xfx_dma_kernel<V, 1024, 1>, 1024, 1);
+    if (ls.block == 256 && ls.ppt == 2) return call(xfx_dma_kernel<V, 256, 2, AS>, 256, 2);
+    if (ls.block == 256 && ls.ppt == 4) return call(xfx_dma_kernel<V, 256, 4, AS>, 256, 4);
+    if (ls.block == 512 && ls.ppt == 1) return call(xfx_dma_kernel<V, 512, 1, AS>, 512, 1);
+    if (ls.block == 512 && ls.ppt == 2) return call(xfx_dma_kernel<V, 512, 2, AS>, 512, 2);
+    if (ls.block == 1024 && ls.ppt == 1) return call(xfx_dma_kernel<V, 1024, 1, AS>, 1024, 1);
     if constexpr (sizeof(V) == 4) {
         if (ls.block == kDmaShapeF32.block && ls.ppt == kDmaShapeF32.ppt)
-            return call(xfx_dma_kernel<V, 512, 4>, 512, 4);
+            return call(xfx_dma_kernel<V, 512, 4, AS>, 512, 4);
     }
     return hipErrorInvalidValue;
 }
 
-template <typename V>
-hipError_t launch_dma_typed(const XfxArgs &a0, LaunchShape ls, int max_blocks, hipStream_t s)
+template <typename V, bool AS>
+hipError_t launch_dma_as(const XfxArgs &a0, LaunchShape ls, int max_blocks, hipStream_t s)
 {
     XfxArgs a = a0;
-    return with_dma_variant<V>(ls, [&](auto fn, int block, int ppt) -> hipError_t {
+    return with_dma_variant<V, AS>(ls, [&](auto fn, int block, int ppt) -> hipError_t {
         const int64_t tile_pts = (int64_t)block * ppt;
         // whole multiples of 16 output rows that fit one slab
         int64_t pass = (int64_t)kDmaNodes * 16 / ((int64_t)a.n_req * (int64_t)sizeof(V)) / 16 * 16;
@@ -353,10 +407,18 @@ hipError_t launch_dma_typed(const XfxArgs &a0, LaunchShape ls, int max_blocks, h
     });
 }
 
+// a.as_out set: the variant that also writes alpha_s.
+template <typename V>
+hipError_t launch_dma_typed(const XfxArgs &a, LaunchShape ls, int max_blocks, hipStream_t s)
+{
+    return a.as_out ? launch_dma_as<V, true>(a, ls, max_blocks, s)
+                    : launch_dma_as<V, false>(a, ls, max_blocks, s);
+}
+
 template <typename V>
 hipError_t dma_occupancy_typed(LaunchShape ls, int *blocks_per_cu)
 {
-    return with_dma_variant<V>(ls, [&](auto fn, int block, int) -> hipError_t {
+    return with_dma_variant<V, false>(ls, [&](auto fn, int block, int) -> hipError_t {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(
             blocks_per_cu, reinterpret_cast<const void *>(fn), block, 0);
     });

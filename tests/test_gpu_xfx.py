@@ -299,3 +299,107 @@ def test_full_size_cfg1_sampled(pdf0, torch, prec):
     got = out[torch.as_tensor(idx, device="cuda")].cpu().numpy()
     check(g, got, x[idx], q2[idx], g.pids, prec, "cfg1-sampled")
     assert bool(torch.isfinite(out).all())
+
+
+def _fused_vs_separate(torch, pdf, pids, x, q2, prec, domain, **kw):
+    """pdfx_eval_xfx_alphas against pdfx_eval_xfx + pdfx_eval_alphas: equal x f
+    bits, alpha_s equal to rounding (its weights are formed inside another
+    kernel, where the compiler may fuse a multiply-add differently: a few ulp),
+    equal NaN pattern and equal domain counts."""
+    xd = torch.as_tensor(x, device="cuda")
+    qd = torch.as_tensor(q2, device="cuda")
+    pdf.domain_errors()
+    a = pdf.xfxQ2(pids, xd, qd, prec=prec, domain=domain, **kw).cpu().numpy()
+    s = pdf.alphasQ2(qd, prec=prec, domain=domain).cpu().numpy()
+    n_sep = pdf.domain_errors()
+    f, fs = pdf.xfx_alphasQ2(pids, xd, qd, prec=prec, domain=domain, **kw)
+    n_fused = pdf.domain_errors()
+    np.testing.assert_array_equal(f.cpu().numpy(), a)
+    fs = fs.cpu().numpy()
+    np.testing.assert_array_equal(np.isnan(fs), np.isnan(s))
+    ok = ~np.isnan(s)
+    assert np.max(np.abs(fs[ok] - s[ok]) / np.abs(s[ok]), initial=0.0) <= (
+        1e-14 if prec == "f64" else 1e-6)
+    assert n_fused == n_sep
+    return a, s
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+@pytest.mark.parametrize("domain", ["nan", "clamp"])
+def test_xfx_alphas_one_call(pdf0, torch, prec, domain):
+    """x f and alpha_s in one call equal the two calls (alpha_s formed from the
+    forward kernel's Q^2 weights: the alpha_s knots of this grid are its Q^2
+    knots), with points outside in x only, in Q^2 only, NaN
+    coordinates and a ragged last tile; alpha_s checked against the oracle."""
+    g = cfg0_grid()
+    x, q2 = cfg0_queries(70_001)
+    x[::97] = 1e-11                 # x below the grid, Q^2 inside
+    q2[5::89] = 0.3                 # Q^2 below the grid, x inside
+    q2[7::101] = 3e10               # Q^2 above
+    x[11::211] = np.nan
+    q2[13::307] = np.nan
+    x[17::401] = 1.0                # last x knot, and a threshold knot below
+    q2[19::503] = g.q2[g.q_off[2]]
+    a, s = _fused_vs_separate(torch, pdf0, list(g.pids), x, q2, prec, domain)
+    ora = oracle.alphas(g.as_q2, g.as_val, q2, mode=0 if domain == "nan" else 1)
+    np.testing.assert_array_equal(np.isnan(s), np.isnan(ora))
+    ok = ~np.isnan(ora)
+    assert np.max(np.abs(s[ok] - ora[ok]) / np.abs(ora[ok])) <= TOL[prec]
+    q_in = (q2 >= g.q2[0]) & (q2 <= g.q2[-1])
+    assert np.isfinite(s[(x == 1e-11) & q_in]).all()      # x outside: alpha_s still defined
+    if domain == "nan":
+        assert np.isnan(a[x == 1e-11]).all()
+
+
+def test_xfx_alphas_other_paths(pdf0, torch, api):
+    """The two-pass fallbacks: an output that only the other kernels take
+    (8-byte aligned, not 16), a request order with repeats, and a grid whose
+    alpha_s knots are not its Q^2 knots."""
+    g = cfg0_grid()
+    x, q2 = cfg0_queries(20_000)
+    n = len(x)
+    for prec in ("f64", "f32s"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        off = 1 if prec == "f64" else 2        # 8 bytes off the 16-byte grain
+        buf = torch.empty(n * 3 + 4, dtype=dt, device="cuda")
+        out = buf[off:off + n * 3].view(n, 3)
+        assert out.data_ptr() % 16 == 8
+        _fused_vs_separate(torch, pdf0, [2, 21, 2], x, q2, prec, "nan", out=out)
+    # 200 x 25 knots: alpha_s values fit the double-buffered kernel's LDS
+    # in FP32 (one pass) but not in FP64 (two passes)
+    rng = np.random.default_rng(7)
+    q2k = np.r_[np.geomspace(1.0, 30.0, 5), np.geomspace(30.0, 1e6, 20)]
+    g4 = wl.GridSpec(pids=np.array([21, 1, -1], dtype=np.int32), x=np.geomspace(1e-7, 1.0, 200),
+                     q2=q2k, q_off=np.array([0, 5, 25], dtype=np.int32),
+                     xf=rng.standard_normal((3, 200, 25)), as_q2=q2k.copy(),
+                     as_val=0.3 / (1.0 + 0.05 * np.log(q2k)))
+    pdf4 = api.mkPDF(g4)
+    xs = np.exp(rng.uniform(math.log(1e-7), 0.0, 5000))
+    qs = np.exp(rng.uniform(0.0, math.log(1e6), 5000))
+    for prec in ("f64", "f32s"):
+        _, s = _fused_vs_separate(torch, pdf4, [21, -1], xs, qs, prec, "nan")
+        ora = oracle.alphas(g4.as_q2, g4.as_val, qs)
+        assert np.max(np.abs(s - ora) / np.abs(ora)) <= TOL[prec]
+    g2 = cfg0_grid()
+    g2.as_q2 = np.geomspace(1.0, 1e10, 37)
+    g2.as_val = 0.3 / (1.0 + 0.05 * np.log(g2.as_q2))
+    pdf2 = api.mkPDF(g2)
+    for prec in ("f64", "f32s"):
+        _, s = _fused_vs_separate(torch, pdf2, list(g2.pids), x, q2, prec, "clamp")
+        ora = oracle.alphas(g2.as_q2, g2.as_val, q2, mode=1)
+        assert np.max(np.abs(s - ora) / np.abs(ora)) <= TOL[prec]
+
+
+def test_xfx_alphas_rejects(pdf0, torch, api):
+    from paper_2012_08221_amd import binding as B
+    g = cfg0_grid()
+    x = torch.full((8,), 0.1, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.PdfxError):
+        pdf0.xfx_alphasQ2(list(g.pids), x, x * 100, domain="extrapolate")
+    g3 = cfg0_grid()
+    g3.as_q2 = np.zeros(0)
+    g3.as_val = np.zeros(0)
+    pdf3 = api.mkPDF(g3)
+    with pytest.raises(B.PdfxError) as e:
+        pdf3.xfx_alphasQ2(list(g.pids), x, x * 100)
+    assert e.value.code == B.PDFX_ENOALPHAS
