@@ -25,7 +25,8 @@
  *    caller values, the adjoint and integrand-gradient workspaces and the
  *    domain counter.  Calls on one handle are ordered by being on one stream;
  *    calls that may run at the same time on different streams need different
- *    handles.
+ *    handles.  A handle also caches launch data on the host (occupancy, the
+ *    workspace size): use each handle from one host thread at a time.
  *  - Eval calls allocate nothing, except that pdfx_eval_xfx_backward and
  *    pdfx_eval_dy_backward grow their handle's workspace (a synchronous device
  *    allocation) the first time they see a larger n; a call sequence meant
