@@ -175,6 +175,19 @@ def main():
             rates[name] = blocks * 256 * iters * 16 / ms / 1e6
         return rates
 
+    def lds_atomic_rates():
+        """FP64 LDS atomic adds per second (pdfx_bench_lds_read modes 2, 3): the
+        ceiling of the knot-gradient scatter."""
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        blocks, iters = cus * 8, 1024
+        sink = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+        rates = {}
+        for mode, name in ((2, "consecutive_per_s"), (3, "random_per_s")):
+            ms = timed(lambda: B.pdfx_bench_lds_read(mode, blocks, iters, sink.data_ptr(),
+                                                     stream.cuda_stream), 5)
+            rates[name] = blocks * 256 * iters / (ms * 1e-3)
+        return rates
+
     if args.calib_copy:
         n, ms, gbs = copy_gbs()
         print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8,
@@ -273,7 +286,9 @@ def main():
             "value": nb * nf / (ms_fb * 1e-3), "unit": "pf/s (forward+backward)",
             "ms_per_step": ms_fb, "forward_ms": ms_f, "backward_ms": ms_fb - ms_f,
             "n_points": nb, "dtype": "f32 stencil forward, FP64 adjoint",
-            "what": "sum w*xf, gradients w.r.t. the 11x100x50 knots, x and Q^2"}
+            "what": "sum w*xf, gradients w.r.t. the 11x100x50 knots, x and Q^2",
+            "knot_scatter_atomics": nb * nf * 16,
+            "lds_atomic_f64": lds_atomic_rates()}
         log("fwd+bwd: %.3f ms (forward %.3f)" % (ms_fb, ms_f))
         if args.only == "bwd":
             print(json.dumps({"only": "bwd", **variants["fwd_bwd"]}))

@@ -306,8 +306,9 @@ def pdfx_grid_shape(h):
 
 
 def pdfx_bench_lds_read(mode: int, blocks: int, iters: int, sink_ptr: int, stream: int):
-    """Enqueues the LDS read micro-benchmark (mode 0 lane-consecutive, 1 random);
-    LDS bytes read = blocks * 256 * iters * 16."""
+    """Enqueues the LDS micro-benchmark: 16-byte reads (mode 0 lane-consecutive,
+    1 random) or FP64 atomic adds (2 lane-consecutive, 3 random);
+    blocks * 256 * iters operations."""
     check(lib().pdfx_bench_lds_read(mode, blocks, iters, sink_ptr, stream))
 
 

@@ -1,9 +1,9 @@
-// LDS read rate of the device, measured: the ceiling the stencil kernels are
-// held to.  Their stencils are aligned 16-byte LDS reads at data-dependent
-// addresses; the two patterns below bracket that: lane-consecutive reads
-// (each wave reads 1 KB in one piece, no bank conflicts) and reads at
-// independent random 16-byte-aligned addresses (the stencil's pattern for
-// points in random order).
+// LDS read and atomic rates of the device, measured: the ceilings the
+// stencil and knot-gradient kernels are held to.  The stencils are aligned
+// 16-byte LDS reads at data-dependent addresses, the knot-gradient scatter
+// FP64 LDS atomic adds; for each, two patterns bracket the kernels' own:
+// lane-consecutive addresses (no bank conflicts) and independent random
+// ones (the pattern for points in random order).
 #include "runtime_internal.h"
 
 namespace pdfx {
@@ -39,6 +39,34 @@ __global__ __launch_bounds__(kMbBlock) void lds_read_kernel(int iters, unsigned 
     sink[(size_t)blockIdx.x * kMbBlock + threadIdx.x] = acc;
 }
 
+// FP64 LDS atomic adds (no return), as the knot-gradient scatter makes them:
+// at lane-consecutive 8-byte addresses, or at independent random ones.
+template <bool RANDOM>
+__global__ __launch_bounds__(kMbBlock) void lds_atomic_kernel(int iters, unsigned seed, double *sink)
+{
+    __shared__ double s[kMbLdsBytes / 8];
+    for (int i = threadIdx.x; i < kMbLdsBytes / 8; i += kMbBlock)
+        s[i] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    unsigned r = seed ^ (threadIdx.x * 2654435761u) ^ (blockIdx.x * 40503u);
+    const double v = 1.0 + threadIdx.x;
+#pragma unroll 8
+    for (int it = 0; it < iters; ++it) {
+        int c;
+        if (RANDOM) {
+            r = r * 1664525u + 1013904223u;
+            c = (int)(r >> 12) & (kMbLdsBytes / 8 - 1);
+        } else {
+            c = ((it * (kMbBlock / 64) + wave) * 64 + lane) & (kMbLdsBytes / 8 - 1);
+        }
+        atomicAdd(&s[c], v);
+    }
+    __syncthreads();
+    sink[(size_t)blockIdx.x * kMbBlock + threadIdx.x] = s[threadIdx.x];
+}
+
 }  // namespace
 }  // namespace pdfx
 
@@ -47,8 +75,8 @@ using namespace pdfx;
 extern "C" int pdfx_bench_lds_read(int mode, int blocks, int iters, double *sink, void *stream)
 {
     clear_error();
-    if (mode != 0 && mode != 1)
-        return fail(PDFX_EINVAL, "unknown mode %d (0 lane-consecutive, 1 random)", mode);
+    if (mode < 0 || mode > 3)
+        return fail(PDFX_EINVAL, "unknown mode %d", mode);
     if (blocks <= 0 || iters <= 0)
         return fail(PDFX_EINVAL, "blocks and iters must be positive");
     if (!sink)
@@ -56,10 +84,14 @@ extern "C" int pdfx_bench_lds_read(int mode, int blocks, int iters, double *sink
     hipStream_t s = (hipStream_t)stream;
     if (mode == 0)
         hipLaunchKernelGGL(lds_read_kernel<false>, dim3(blocks), dim3(kMbBlock), 0, s, iters, 1u, sink);
-    else
+    else if (mode == 1)
         hipLaunchKernelGGL(lds_read_kernel<true>, dim3(blocks), dim3(kMbBlock), 0, s, iters, 1u, sink);
+    else if (mode == 2)
+        hipLaunchKernelGGL(lds_atomic_kernel<false>, dim3(blocks), dim3(kMbBlock), 0, s, iters, 1u, sink);
+    else
+        hipLaunchKernelGGL(lds_atomic_kernel<true>, dim3(blocks), dim3(kMbBlock), 0, s, iters, 1u, sink);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
-        return fail_hip(e, "LDS read launch");
+        return fail_hip(e, "LDS micro-benchmark launch");
     return PDFX_OK;
 }

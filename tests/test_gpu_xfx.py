@@ -286,19 +286,24 @@ def test_caller_values_match_owned(pdf0, torch):
 
 @pytest.mark.parametrize("prec", ["f64", "f32s"])
 def test_full_size_cfg1_sampled(pdf0, torch, prec):
-    """1e7 points x 11 flavours in the benchmark's launch configuration;
-    20000 sampled points checked against the oracle."""
+    """1e7 points x 11 flavours and alpha_s: the benchmark step's call
+    (pdfx_eval_xfx_alphas) in its launch configuration; 20000 sampled points
+    checked against the oracle."""
     g = cfg0_grid()
     n = 10_000_000
     x, q2 = wl.queries(1, n)
     xd = torch.as_tensor(x, device="cuda")
     qd = torch.as_tensor(q2, device="cuda")
-    out = pdf0.xfxQ2(g.pids, xd, qd, prec=prec)
+    out, a = pdf0.xfx_alphasQ2(g.pids, xd, qd, prec=prec)
     idx = np.random.default_rng(3).choice(n, 20_000, replace=False)
     idx = np.r_[idx, [0, n - 1]]
-    got = out[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    ti = torch.as_tensor(idx, device="cuda")
+    got = out[ti].cpu().numpy()
     check(g, got, x[idx], q2[idx], g.pids, prec, "cfg1-sampled")
-    assert bool(torch.isfinite(out).all())
+    ga = a[ti].double().cpu().numpy()
+    ora = oracle.alphas(g.as_q2, g.as_val, q2[idx])
+    assert np.max(np.abs(ga - ora) / np.abs(ora)) <= TOL[prec]
+    assert bool(torch.isfinite(out).all()) and bool(torch.isfinite(a).all())
 
 
 def _fused_vs_separate(torch, pdf, pids, x, q2, prec, domain, **kw):
