@@ -184,12 +184,18 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
 // from the state pass) is read and its weights folded once per group rather
 // than once per flavour.  The LDS sums are added to the FP64 accumulator at
 // the end.
+//
+// The scatter is bound by FP64 LDS atomics.  A point's 16 adds go to its
+// stencil base plus offsets common to all lanes, so each wave first deals its
+// 64 points out to lanes by the base's bank (wave_deal); only the point index
+// moves, and invalid points sort last and are skipped.
 constexpr int kKnotGroup = 3;
 constexpr int kKnotBlock = 1024;
 
 __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
 {
     __shared__ double gsl[kKnotGroup][kDmaNodes];
+    __shared__ int khist[kKnotBlock / 64][kDealKeys];
     const BwdArgs &a = k.b;
     const int grp = blockIdx.y;
     const int u0 = grp * kKnotGroup;
@@ -201,7 +207,25 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
     __syncthreads();
     const int64_t p_begin = (int64_t)blockIdx.x * a.chunk;
     const int64_t p_end = p_begin + a.chunk < a.n ? p_begin + a.chunk : a.n;
-    for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kKnotBlock) {
+    const int lane = threadIdx.x & 63;
+    int *hist = khist[threadIdx.x >> 6];
+    // wave-uniform loop: every lane takes part in the reordering
+    for (int64_t p0 = p_begin + (threadIdx.x & ~63); p0 < p_end; p0 += kKnotBlock) {
+        int key = kDealKeys - 1;
+        {
+            const int64_t pn = p0 + lane;
+            const int64_t pc = pn < p_end ? pn : p_end - 1;   // clamped: a global load
+            const int idx = a.st_idx[pc];
+            if (pn < p_end && !(a.st_flag[pc] & 1)) {
+                int sx = (idx & 0xffff) - 1, sq = (idx >> 16) - 1;
+                sx = sx < 0 ? 0 : (sx > nx - 4 ? nx - 4 : sx);
+                sq = sq < 0 ? 0 : (sq > nq - 4 ? nq - 4 : sq);
+                key = (sx * nq + sq) & 31;
+            }
+        }
+        const int64_t p = p0 + wave_deal(key, hist);
+        if (p >= p_end)
+            continue;
         if (a.st_flag[p] & 1)   // outside the grid (NaN mode) or NaN input
             continue;
         const int idx = a.st_idx[p];

@@ -308,7 +308,10 @@ hipError_t dy_dma_typed(const DyArgs &a, LaunchShape ls, int cus, hipStream_t s,
 // state (bins, local coordinates, alpha_s from the state pass) is read and its
 // weights folded once for the two flavours, and each partner value comes from
 // a 16-tap stencil of the other flavour's slab.  The LDS gradients are added
-// to the FP64 accumulator at the end.
+// to the FP64 accumulator at the end.  The scatter is bound by FP64 LDS
+// atomics: each wave deals its points out to lanes by the bank of the quark
+// stencil's base (wave_deal), which spreads the quark half of the adds over
+// the banks; the antiquark half stays in point order.
 
 constexpr int kPairBlock = 1024;
 
@@ -320,6 +323,7 @@ __global__ __launch_bounds__(kPairBlock) void dy_pair_adjoint_kernel(const DyArg
     __shared__ V vqb[kDmaNodes];
     __shared__ double gq[kDmaNodes];
     __shared__ double gqb[kDmaNodes];
+    __shared__ int khist[kPairBlock / 64][kDealKeys];
     const int q = blockIdx.y + 1;          // quark q: row 5 + q; antiquark: row 5 - q
     const int rq = 5 + q, rqb = 5 - q;
     const int nx = a.nx, nq = a.nq, nodes = nx * nq;
@@ -333,7 +337,25 @@ __global__ __launch_bounds__(kPairBlock) void dy_pair_adjoint_kernel(const DyArg
     __syncthreads();
     const int64_t p_begin = (int64_t)blockIdx.x * a.chunk;
     const int64_t p_end = p_begin + a.chunk < a.n ? p_begin + a.chunk : a.n;
-    for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kPairBlock) {
+    const int lane = threadIdx.x & 63;
+    int *hist = khist[threadIdx.x >> 6];
+    // wave-uniform loop: every lane takes part in the dealing
+    for (int64_t p0 = p_begin + (threadIdx.x & ~63); p0 < p_end; p0 += kPairBlock) {
+        int key = kDealKeys - 1;
+        {
+            const int64_t pn = p0 + lane;
+            const int64_t pc = pn < p_end ? pn : p_end - 1;   // clamped: a global load
+            const int idx = a.st_i1[pc];
+            if (pn < p_end && idx >= 0) {
+                int sx = (idx & 0xffff) - 1, sq = (idx >> 16) - 1;
+                sx = sx < 0 ? 0 : (sx > nx - 4 ? nx - 4 : sx);
+                sq = sq < 0 ? 0 : (sq > nq - 4 ? nq - 4 : sq);
+                key = (sx * nq + sq) & 31;
+            }
+        }
+        const int64_t p = p0 + wave_deal(key, hist);
+        if (p >= p_end)
+            continue;
         const int idx1 = a.st_i1[p];
         if (idx1 < 0)
             continue;

@@ -36,6 +36,38 @@ __device__ __forceinline__ double load_point(const double *v, int64_t p, int64_t
     return v[p < n ? p : n - 1];
 }
 
+// Keys of the in-wave dealing below: 32 LDS bank keys of an 8-byte word
+// (its index mod 32) and one for lanes that do no work.
+constexpr int kDealKeys = 33;
+
+// In-wave dealing for LDS atomic scatters, which run ~2.7x faster when the
+// lanes of one instruction hit different banks: the 64 lanes' keys (in
+// [0, kDealKeys), the last for idle lanes) are counting-sorted and sorted rank
+// r goes to lane (r mod 4) * 16 + r / 4, so that every 16 lanes hold keys
+// spread over the sorted order.  Returns the lane whose item this lane takes.
+// hist: this wave's kDealKeys ints of LDS.  Every lane of the wave must call
+// it together.
+__device__ __forceinline__ int wave_deal(int key, int *hist)
+{
+    const int lane = threadIdx.x & 63;
+    if (lane < kDealKeys)
+        hist[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const int lrank = atomicAdd(&hist[key], 1);   // rank among the wave's equal keys
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = lane < kDealKeys ? hist[lane] : 0;
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d)
+            incl += t;
+    }
+    const int rank = __shfl(incl - cnt, key) + lrank;
+    const int dest = (rank & 3) * 16 + (rank >> 2);
+    return __builtin_amdgcn_ds_permute(dest * 4, lane);
+}
+
 // Device view of one axis (global-memory tables).
 struct AxisDev {
     const double *knots;          // raw knots, non-decreasing (search on raw values)
