@@ -163,27 +163,27 @@ def main():
         return n, ms, 2 * n * 8 / ms / 1e6
 
     def lds_read_gbs():
-        """LDS read rates the device reaches (pdfx_bench_lds_read, 8 workgroups
+        """LDS read rates the device reaches (pdfx_bench_lds, 8 workgroups
         per CU): aligned 16-byte reads, lane-consecutive and at random addresses."""
         cus = torch.cuda.get_device_properties(dev).multi_processor_count
         blocks, iters = cus * 8, 4096
         sink = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
         rates = {}
         for mode, name in ((0, "measured_stream_gbs"), (1, "measured_random_gbs")):
-            ms = timed(lambda: B.pdfx_bench_lds_read(mode, blocks, iters, sink.data_ptr(),
+            ms = timed(lambda: B.pdfx_bench_lds(mode, blocks, iters, sink.data_ptr(),
                                                      stream.cuda_stream), 5)
             rates[name] = blocks * 256 * iters * 16 / ms / 1e6
         return rates
 
     def lds_atomic_rates():
-        """FP64 LDS atomic adds per second (pdfx_bench_lds_read modes 2, 3): the
+        """FP64 LDS atomic adds per second (pdfx_bench_lds modes 2, 3): the
         ceiling of the knot-gradient scatter."""
         cus = torch.cuda.get_device_properties(dev).multi_processor_count
         blocks, iters = cus * 8, 1024
         sink = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
         rates = {}
         for mode, name in ((2, "consecutive_per_s"), (3, "random_per_s")):
-            ms = timed(lambda: B.pdfx_bench_lds_read(mode, blocks, iters, sink.data_ptr(),
+            ms = timed(lambda: B.pdfx_bench_lds(mode, blocks, iters, sink.data_ptr(),
                                                      stream.cuda_stream), 5)
             rates[name] = blocks * 256 * iters / (ms * 1e-3)
         return rates
@@ -498,7 +498,7 @@ def main():
         lb = lds_bytes(prec, r["launch"], n, nf, grid.n_x, grid.n_q)
         if lb is not None:
             # LDS ceiling: the rates the device is measured to reach in this
-            # run (pdfx_bench_lds_read), lane-consecutive reads as the peak
+            # run (pdfx_bench_lds), lane-consecutive reads as the peak
             ach = lb / (r["xfx_ms"] * 1e-3) / 1e9
             peak = lds_meas["measured_stream_gbs"]
             variants[prec]["lds"] = {

@@ -290,7 +290,7 @@ int pdfx_domain_errors(const pdfx_grid *g, int64_t *count);
  * times the call on `stream`.  `sink`: device, blocks * 256 doubles, receives
  * per-thread values so that the work is kept.  PDFX_EINVAL for another mode,
  * blocks or iters <= 0, or a NULL sink.  Asynchronous on stream. */
-int pdfx_bench_lds_read(int mode, int blocks, int iters, double *sink, void *stream);
+int pdfx_bench_lds(int mode, int blocks, int iters, double *sink, void *stream);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char *pdfx_last_error(void);

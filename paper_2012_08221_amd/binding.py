@@ -45,7 +45,7 @@ EXPORTS = (
     "pdfx_autotune", "pdfx_autotune_set", "pdfx_get_launch", "pdfx_set_launch",
     "pdfx_get_dy_launch", "pdfx_set_dy_launch",
     "pdfx_eval_lumi", "pdfx_get_lumi_launch", "pdfx_set_lumi_launch",
-    "pdfx_domain_errors", "pdfx_bench_lds_read", "pdfx_last_error", "pdfx_version",
+    "pdfx_domain_errors", "pdfx_bench_lds", "pdfx_last_error", "pdfx_version",
 )
 
 
@@ -111,7 +111,7 @@ def lib():
             "pdfx_get_lumi_launch": ([vp, i32, vp, vp], i32),
             "pdfx_set_lumi_launch": ([vp, i32, i32, i32], i32),
             "pdfx_domain_errors": ([vp, vp], i32),
-            "pdfx_bench_lds_read": ([i32, i32, i32, vp, vp], i32),
+            "pdfx_bench_lds": ([i32, i32, i32, vp, vp], i32),
             "pdfx_last_error": ([], ctypes.c_char_p),
             "pdfx_version": ([], ctypes.c_char_p),
         }
@@ -305,11 +305,11 @@ def pdfx_grid_shape(h):
     return tuple(a.value for a in v)
 
 
-def pdfx_bench_lds_read(mode: int, blocks: int, iters: int, sink_ptr: int, stream: int):
+def pdfx_bench_lds(mode: int, blocks: int, iters: int, sink_ptr: int, stream: int):
     """Enqueues the LDS micro-benchmark: 16-byte reads (mode 0 lane-consecutive,
     1 random) or FP64 atomic adds (2 lane-consecutive, 3 random);
     blocks * 256 * iters operations."""
-    check(lib().pdfx_bench_lds_read(mode, blocks, iters, sink_ptr, stream))
+    check(lib().pdfx_bench_lds(mode, blocks, iters, sink_ptr, stream))
 
 
 def pdfx_version() -> str:

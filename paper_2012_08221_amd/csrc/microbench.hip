@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kMbBlock) void lds_atomic_kernel(int iters, unsigne
 
 using namespace pdfx;
 
-extern "C" int pdfx_bench_lds_read(int mode, int blocks, int iters, double *sink, void *stream)
+extern "C" int pdfx_bench_lds(int mode, int blocks, int iters, double *sink, void *stream)
 {
     clear_error();
     if (mode < 0 || mode > 3)
