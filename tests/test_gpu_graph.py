@@ -1,6 +1,6 @@
 """The eval calls inside a captured HIP graph (torch.cuda.CUDAGraph): forward
-x f in both precisions, alpha_s, the continuation mode, the luminosity, a set
-of members and the integrand forward.  The graph is replayed several times,
+x f in both precisions, alpha_s, x f and alpha_s in one pass, the continuation
+mode, the luminosity, a set of members and the integrand forward.  The graph is replayed several times,
 with new inputs copied in and eager work and synchronisations between the
 replays; every replay must give the eager result's bits."""
 import numpy as np
@@ -36,6 +36,8 @@ def test_eval_calls_replay_in_a_graph(torch):
     o32 = torch.empty((n, 11), dtype=torch.float32, device=dev)
     oex = torch.empty((n, 11), dtype=torch.float64, device=dev)
     oas = torch.empty(n, dtype=torch.float64, device=dev)
+    o1 = torch.empty((n, 11), dtype=torch.float64, device=dev)
+    o1as = torch.empty(n, dtype=torch.float64, device=dev)
     oset = torch.empty((6, n, 3), dtype=torch.float64, device=dev)
 
     def inputs(k):
@@ -52,13 +54,14 @@ def test_eval_calls_replay_in_a_graph(torch):
         pdf.xfxQ2(pids, x, q2, prec="f32s", out=o32)
         pdf.xfxQ2(pids, x, q2, out=oex, domain="extrapolate")
         pdf.alphasQ2(q2, out=oas)
+        pdf.xfx_alphasQ2(pids, x, q2, out=o1, as_out=o1as)
         pset.xfxQ2([21, 1, -2], x, q2, out=oset)
         L, S = pdf.lumi([5, 5], [2, -1], x, torch.flip(x, [0]), q2=q2)
         I, _ = api.dy_integrand(pdf, u1, u2, wl.DY_XMIN, wl.SQRT_S_DY ** 2)
         return L, S, I
 
     def snapshot(L, S, I):
-        return [t.cpu().numpy().copy() for t in (o64, o32, oex, oas, oset, L, S, I)]
+        return [t.cpu().numpy().copy() for t in (o64, o32, oex, oas, o1, o1as, oset, L, S, I)]
 
     inputs(0)
     work()                                     # warm-up outside the capture
@@ -70,7 +73,7 @@ def test_eval_calls_replay_in_a_graph(torch):
         inputs(k)
         want = snapshot(*work())               # eager, same inputs
         torch.cuda.synchronize()
-        for t in (o64, o32, oex, oas, oset, Lg, Sg, Ig):
+        for t in (o64, o32, oex, oas, o1, o1as, oset, Lg, Sg, Ig):
             t.fill_(np.nan)
         graph.replay()
         torch.cuda.synchronize()
@@ -78,3 +81,4 @@ def test_eval_calls_replay_in_a_graph(torch):
         for a, b in zip(got, want):
             np.testing.assert_array_equal(a, b)
         assert np.isfinite(got[2]).all()       # the continuation rewrote the outside rows
+        np.testing.assert_array_equal(got[4], got[0])   # one-pass x f = x f alone
