@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline step")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
-    ap.add_argument("--only", default=None, choices=["xfx", "members", "dy", "bwd", "lumi"],
+    ap.add_argument("--only", default=None, choices=["xfx", "members", "folder", "dy", "bwd", "lumi"],
                     help="run one workload for a few steps (profiler runs) and print its timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain copy kernel of known size (counter scaling) and exit")
@@ -317,6 +317,38 @@ def main():
         del pset
         if args.only == "members":
             print(json.dumps({"only": "members", **variants["members"]}))
+            return
+
+    # The same 101 members as a set folder in the standard grid format: written
+    # out (not timed), then read back on the host and read back onto the GPU
+    if args.only == "folder" or (args.only is None and not args.no_extra):
+        import shutil
+        import tempfile
+        from paper_2012_08221_amd import lhapdf
+        members = wl.member_grids(101)
+        tmp = tempfile.mkdtemp()
+        try:
+            folder = lhapdf.write_set(tmp, "SYNTH101", members)
+            text = sum(os.path.getsize(os.path.join(folder, f)) for f in os.listdir(folder))
+            t0 = time.perf_counter()
+            lhapdf.load_set("SYNTH101", tmp)
+            t_parse = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            pset = api.PDFSet("SYNTH101", tmp)
+            torch.cuda.synchronize()
+            t_set = time.perf_counter() - t0
+            del pset
+        finally:
+            shutil.rmtree(tmp, ignore_errors=True)
+        variants["grid_folder"] = {
+            "n_members": 101, "text_mb": text / 1e6, "parse_s": t_parse,
+            "parse_mb_per_s": text / 1e6 / t_parse, "pdfset_from_folder_s": t_set,
+            "what": "host reader of the standard grid format; PDFSet(name, dir) = read + "
+                    "validate + device upload of every member"}
+        log("grid folder: %.0f MB parsed in %.2f s; PDFSet from the folder %.2f s"
+            % (text / 1e6, t_parse, t_set))
+        if args.only == "folder":
+            print(json.dumps({"only": "folder", **variants["grid_folder"]}))
             return
 
     # Drell-Yan-like integrand, 1e8 points in 10 chunks of 1e7
