@@ -11,6 +11,7 @@
 // whatever the values' precision.
 #include "bwd_internal.h"
 #include "xfx_dma_impl.h"
+#include "fixed_point.h"
 
 namespace pdfx {
 
@@ -185,17 +186,21 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
 // than once per flavour.  The LDS sums are added to the FP64 accumulator at
 // the end.
 //
-// The scatter is bound by FP64 LDS atomics.  A point's 16 adds go to its
-// stencil base plus offsets common to all lanes, so each wave first deals its
-// 64 points out to lanes by the base's bank (wave_deal); only the point index
-// moves, and invalid points sort last and are skipped.
+// The scatter is bound by LDS atomics.  A point's 16 adds go to its stencil
+// base plus offsets common to all lanes, so each wave first deals its 64
+// points out to lanes by the base's bank (wave_deal); only the point index
+// moves, and invalid points sort last and are skipped.  The sums are kept in
+// 64-bit fixed point (fixed_point.h): per flavour, a sweep over the chunk
+// finds max |dL/dout| and the scale follows from it and the axes' weight-sum
+// bounds.  Non-finite dL/dout makes that flavour's gradient NaN.
 constexpr int kKnotGroup = 3;
 constexpr int kKnotBlock = 1024;
 
 __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
 {
-    __shared__ double gsl[kKnotGroup][kDmaNodes];
+    __shared__ unsigned long long gsl[kKnotGroup][kDmaNodes];
     __shared__ int khist[kKnotBlock / 64][kDealKeys];
+    __shared__ double wmax[kKnotGroup + 2][kKnotBlock / 64];
     const BwdArgs &a = k.b;
     const int grp = blockIdx.y;
     const int u0 = grp * kKnotGroup;
@@ -203,14 +208,67 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
     const int nx = a.nx, nq = a.nq, nodes = nx * nq;
     for (int e = threadIdx.x; e < nodes; e += kKnotBlock)
         for (int j = 0; j < kKnotGroup; ++j)
-            gsl[j][e] = 0.0;
-    __syncthreads();
+            gsl[j][e] = 0ull;
     const int64_t p_begin = (int64_t)blockIdx.x * a.chunk;
     const int64_t p_end = p_begin + a.chunk < a.n ? p_begin + a.chunk : a.n;
+    auto gval = [&](int u, int64_t p) {
+        double g = 0.0;
+        for (int c = a.ucol_off[u]; c < a.ucol_off[u + 1]; ++c)
+            g += k.f32 ? (double)reinterpret_cast<const float *>(a.gout)[p * a.n_req + a.ucols[c]]
+                       : reinterpret_cast<const double *>(a.gout)[p * a.n_req + a.ucols[c]];
+        return g;
+    };
+    // m[j]: max |dL/dout| of flavour j over the chunk's points; m[kKnotGroup],
+    // m[kKnotGroup + 1]: weight-sum bounds of the x and Q^2 axes
+    double m[kKnotGroup + 2];
+#pragma unroll
+    for (int j = 0; j < kKnotGroup + 2; ++j)
+        m[j] = 0.0;
+    for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kKnotBlock) {
+        if (a.st_flag[p] & 1)
+            continue;
+#pragma unroll
+        for (int j = 0; j < kKnotGroup; ++j)
+            if (j < nu)
+                m[j] = nan_max(m[j], fabs(gval(u0 + j, p)));
+    }
+    for (int i = threadIdx.x; i < nx - 1; i += kKnotBlock)
+        m[kKnotGroup] = fmax(m[kKnotGroup], weight_sum_bound(a.ax.rec64[i]));
+    for (int i = threadIdx.x; i < nq - 1; i += kKnotBlock)
+        m[kKnotGroup + 1] = fmax(m[kKnotGroup + 1], weight_sum_bound(a.aq.rec64[i]));
+#pragma unroll
+    for (int j = 0; j < kKnotGroup + 2; ++j) {
+        double v = m[j];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1)
+            v = nan_max(v, __shfl_xor(v, d));
+        if ((threadIdx.x & 63) == 0)
+            wmax[j][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kKnotGroup + 2; ++j) {
+        double v = wmax[j][0];
+        for (int w = 1; w < kKnotBlock / 64; ++w)
+            v = nan_max(v, wmax[j][w]);
+        m[j] = v;
+    }
+    double fs[kKnotGroup];
+    int es[kKnotGroup];
+    bool fin[kKnotGroup];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < kKnotGroup; ++j) {
+        const double bnd = m[j] * m[kKnotGroup] * m[kKnotGroup + 1];   // |g wx wq|
+        fin[j] = bnd < 1.0 / 0.0;                                      // false for NaN
+        any = any || (j < nu && fin[j]);
+        es[j] = fin[j] ? fixed_exponent(bnd, p_end - p_begin) : 0;
+        fs[j] = ldexp(1.0, es[j]);
+    }
     const int lane = threadIdx.x & 63;
     int *hist = khist[threadIdx.x >> 6];
     // wave-uniform loop: every lane takes part in the reordering
-    for (int64_t p0 = p_begin + (threadIdx.x & ~63); p0 < p_end; p0 += kKnotBlock) {
+    for (int64_t p0 = p_begin + (threadIdx.x & ~63); any && p0 < p_end; p0 += kKnotBlock) {
         int key = kDealKeys - 1;
         {
             const int64_t pn = p0 + lane;
@@ -238,18 +296,14 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
         const int base = fwd::window(ix, nx, wx) * nq + fwd::window(kq, nq, wq);
 #pragma unroll
         for (int j = 0; j < kKnotGroup; ++j) {
-            if (j < nu) {
-                const int u = u0 + j;
-                double g = 0.0;
-                for (int c = a.ucol_off[u]; c < a.ucol_off[u + 1]; ++c)
-                    g += k.f32 ? (double)reinterpret_cast<const float *>(a.gout)[p * a.n_req + a.ucols[c]]
-                               : reinterpret_cast<const double *>(a.gout)[p * a.n_req + a.ucols[c]];
+            if (j < nu && fin[j]) {
+                const double g = gval(u0 + j, p);
 #pragma unroll
                 for (int jx = 0; jx < 4; ++jx) {
                     const double gx = g * wx[jx];
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk)
-                        atomicAdd(&gsl[j][base + jx * nq + kk], gx * wq[kk]);
+                        atomicAdd(&gsl[j][base + jx * nq + kk], to_fixed(gx * wq[kk], fs[j]));
                 }
             }
         }
@@ -257,9 +311,14 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
     __syncthreads();
     for (int j = 0; j < nu; ++j) {
         double *dst = a.gacc + (size_t)a.urow[u0 + j] * nodes;
-        for (int e = threadIdx.x; e < nodes; e += kKnotBlock)
-            if (gsl[j][e] != 0.0)
-                unsafeAtomicAdd(&dst[e], gsl[j][e]);
+        const double inv = ldexp(1.0, -es[j]);
+        for (int e = threadIdx.x; e < nodes; e += kKnotBlock) {
+            const long long v = (long long)gsl[j][e];
+            if (!fin[j])
+                unsafeAtomicAdd(&dst[e], __builtin_nan(""));
+            else if (v != 0)
+                unsafeAtomicAdd(&dst[e], (double)v * inv);
+        }
     }
 }
 

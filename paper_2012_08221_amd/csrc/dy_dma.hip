@@ -15,6 +15,7 @@
 // by bisection over its knots in LDS, its interval records and values are
 // read from global memory.
 #include "xfx_dma_impl.h"
+#include "fixed_point.h"
 
 namespace pdfx {
 
@@ -323,36 +324,6 @@ hipError_t dy_dma_typed(const DyArgs &a, LaunchShape ls, int cus, hipStream_t s,
 
 constexpr int kPairBlock = 1024;
 
-// Larger of a and b; NaN if either is NaN.
-__device__ __forceinline__ double nan_max(double a, double b)
-{
-    return (b > a || b != b) ? b : a;
-}
-
-// Bound on the sum of |folded weights| over t in [0, 1] for one interval.
-__device__ __forceinline__ double weight_sum_bound(const IntervalRec<double> &r)
-{
-    return 1.0 + (4.0 / 27.0) * (fabs(r.pl) + fabs(r.plql) + fabs(r.ql) + fabs(r.qr) +
-                                 fabs(r.qrpr) + fabs(r.pr));
-}
-
-// Round-to-nearest fixed point of c * f (|c * f| < 2^51): adding 1.5 * 2^52
-// leaves the integer in the low mantissa bits.
-__device__ __forceinline__ unsigned long long to_fixed(double c, double f)
-{
-    const double t = fma(c, f, 6755399441055744.0);
-    return (unsigned long long)(__double_as_longlong(t) - 0x4338000000000000LL);
-}
-
-// Fixed-point exponent for terms bounded by bnd, summed at most n at a time.
-__device__ __forceinline__ int fixed_exponent(double bnd, int64_t n)
-{
-    int lc, lb;
-    frexp((double)n, &lc);   // n < 2^lc
-    frexp(bnd, &lb);         // bnd < 2^lb (0 for bnd = 0)
-    const int smax = 61 - lc < 50 ? 61 - lc : 50;
-    return smax - lb;
-}
 
 template <typename V>
 __global__ __launch_bounds__(kPairBlock) void dy_pair_adjoint_kernel(const DyArgs a)
