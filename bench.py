@@ -176,13 +176,15 @@ def main():
         return rates
 
     def lds_atomic_rates():
-        """FP64 LDS atomic adds per second (pdfx_bench_lds modes 2, 3): the
-        ceiling of the knot-gradient scatter."""
+        """64-bit LDS atomic adds per second (pdfx_bench_lds modes 2-5), FP64 and
+        integer: the ceilings of the gradient scatters (fixed-point sums use the
+        integer adds)."""
         cus = torch.cuda.get_device_properties(dev).multi_processor_count
         blocks, iters = cus * 8, 1024
         sink = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
         rates = {}
-        for mode, name in ((2, "consecutive_per_s"), (3, "random_per_s")):
+        for mode, name in ((2, "f64_consecutive_per_s"), (3, "f64_random_per_s"),
+                           (4, "u64_consecutive_per_s"), (5, "u64_random_per_s")):
             ms = timed(lambda: B.pdfx_bench_lds(mode, blocks, iters, sink.data_ptr(),
                                                      stream.cuda_stream), 5)
             rates[name] = blocks * 256 * iters / (ms * 1e-3)
@@ -288,7 +290,7 @@ def main():
             "n_points": nb, "dtype": "f32 stencil forward, FP64 adjoint",
             "what": "sum w*xf, gradients w.r.t. the 11x100x50 knots, x and Q^2",
             "knot_scatter_atomics": nb * nf * 16,
-            "lds_atomic_f64": lds_atomic_rates()}
+            "lds_atomic_64bit": lds_atomic_rates()}
         log("fwd+bwd: %.3f ms (forward %.3f)" % (ms_fb, ms_f))
         if args.only == "bwd":
             print(json.dumps({"only": "bwd", **variants["fwd_bwd"]}))

@@ -280,13 +280,14 @@ int pdfx_domain_errors(const pdfx_grid *g, int64_t *count);
 
 /* Measurement helper, not part of the method: the device's rate of aligned
  * 16-byte LDS reads, the ceiling of the stencil kernels (their stencils are
- * such reads at data-dependent addresses), and of FP64 LDS atomic adds, the
- * ceiling of the knot-gradient scatter.  Enqueues `blocks` workgroups of 256
+ * such reads at data-dependent addresses), and of 64-bit LDS atomic adds, the
+ * ceiling of the gradient scatters.  Enqueues `blocks` workgroups of 256
  * threads; each thread makes `iters` operations on a 64 KB LDS array:
  * 16-byte reads, lane-consecutive (mode 0: each wave reads 1 KB in one
  * piece) or at independent random 16-byte-aligned addresses (mode 1); FP64
  * atomic adds, lane-consecutive (mode 2) or at random 8-byte-aligned
- * addresses (mode 3).  Operations per call = blocks * 256 * iters; the caller
+ * addresses (mode 3); 64-bit integer atomic adds, the same two ways (modes 4,
+ * 5).  Operations per call = blocks * 256 * iters; the caller
  * times the call on `stream`.  `sink`: device, blocks * 256 doubles, receives
  * per-thread values so that the work is kept.  PDFX_EINVAL for another mode,
  * blocks or iters <= 0, or a NULL sink.  Asynchronous on stream. */

@@ -307,7 +307,8 @@ def pdfx_grid_shape(h):
 
 def pdfx_bench_lds(mode: int, blocks: int, iters: int, sink_ptr: int, stream: int):
     """Enqueues the LDS micro-benchmark: 16-byte reads (mode 0 lane-consecutive,
-    1 random) or FP64 atomic adds (2 lane-consecutive, 3 random);
+    1 random), FP64 atomic adds (2 lane-consecutive, 3 random) or 64-bit
+    integer atomic adds (4, 5);
     blocks * 256 * iters operations."""
     check(lib().pdfx_bench_lds(mode, blocks, iters, sink_ptr, stream))
 

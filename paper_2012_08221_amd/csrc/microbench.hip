@@ -1,7 +1,8 @@
 // LDS read and atomic rates of the device, measured: the ceilings the
-// stencil and knot-gradient kernels are held to.  The stencils are aligned
-// 16-byte LDS reads at data-dependent addresses, the knot-gradient scatter
-// FP64 LDS atomic adds; for each, two patterns bracket the kernels' own:
+// stencil and gradient kernels are held to.  The stencils are aligned
+// 16-byte LDS reads at data-dependent addresses, the gradient scatters 64-bit
+// LDS atomic adds (FP64, or integer for fixed-point sums); for each, two
+// patterns bracket the kernels' own:
 // lane-consecutive addresses (no bank conflicts) and independent random
 // ones (the pattern for points in random order).
 #include "runtime_internal.h"
@@ -39,19 +40,20 @@ __global__ __launch_bounds__(kMbBlock) void lds_read_kernel(int iters, unsigned 
     sink[(size_t)blockIdx.x * kMbBlock + threadIdx.x] = acc;
 }
 
-// FP64 LDS atomic adds (no return), as the knot-gradient scatter makes them:
-// at lane-consecutive 8-byte addresses, or at independent random ones.
-template <bool RANDOM>
+// 64-bit LDS atomic adds (no return), FP64 or integer (T), as the gradient
+// scatters make them: at lane-consecutive 8-byte addresses, or at
+// independent random ones.
+template <typename T, bool RANDOM>
 __global__ __launch_bounds__(kMbBlock) void lds_atomic_kernel(int iters, unsigned seed, double *sink)
 {
-    __shared__ double s[kMbLdsBytes / 8];
+    __shared__ T s[kMbLdsBytes / 8];
     for (int i = threadIdx.x; i < kMbLdsBytes / 8; i += kMbBlock)
-        s[i] = 0.0;
+        s[i] = T(0);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     unsigned r = seed ^ (threadIdx.x * 2654435761u) ^ (blockIdx.x * 40503u);
-    const double v = 1.0 + threadIdx.x;
+    const T v = T(1 + threadIdx.x);
 #pragma unroll 8
     for (int it = 0; it < iters; ++it) {
         int c;
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(kMbBlock) void lds_atomic_kernel(int iters, unsigne
         atomicAdd(&s[c], v);
     }
     __syncthreads();
-    sink[(size_t)blockIdx.x * kMbBlock + threadIdx.x] = s[threadIdx.x];
+    sink[(size_t)blockIdx.x * kMbBlock + threadIdx.x] = (double)s[threadIdx.x];
 }
 
 }  // namespace
@@ -75,7 +77,7 @@ using namespace pdfx;
 extern "C" int pdfx_bench_lds(int mode, int blocks, int iters, double *sink, void *stream)
 {
     clear_error();
-    if (mode < 0 || mode > 3)
+    if (mode < 0 || mode > 5)
         return fail(PDFX_EINVAL, "unknown mode %d", mode);
     if (blocks <= 0 || iters <= 0)
         return fail(PDFX_EINVAL, "blocks and iters must be positive");
@@ -87,9 +89,17 @@ extern "C" int pdfx_bench_lds(int mode, int blocks, int iters, double *sink, voi
     else if (mode == 1)
         hipLaunchKernelGGL(lds_read_kernel<true>, dim3(blocks), dim3(kMbBlock), 0, s, iters, 1u, sink);
     else if (mode == 2)
-        hipLaunchKernelGGL(lds_atomic_kernel<false>, dim3(blocks), dim3(kMbBlock), 0, s, iters, 1u, sink);
+        hipLaunchKernelGGL((lds_atomic_kernel<double, false>), dim3(blocks), dim3(kMbBlock), 0, s,
+                           iters, 1u, sink);
+    else if (mode == 3)
+        hipLaunchKernelGGL((lds_atomic_kernel<double, true>), dim3(blocks), dim3(kMbBlock), 0, s,
+                           iters, 1u, sink);
+    else if (mode == 4)
+        hipLaunchKernelGGL((lds_atomic_kernel<unsigned long long, false>), dim3(blocks),
+                           dim3(kMbBlock), 0, s, iters, 1u, sink);
     else
-        hipLaunchKernelGGL(lds_atomic_kernel<true>, dim3(blocks), dim3(kMbBlock), 0, s, iters, 1u, sink);
+        hipLaunchKernelGGL((lds_atomic_kernel<unsigned long long, true>), dim3(blocks),
+                           dim3(kMbBlock), 0, s, iters, 1u, sink);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail_hip(e, "LDS micro-benchmark launch");

@@ -82,7 +82,7 @@ def test_null_arguments_rejected(L):
     assert L.pdfx_grid_shape(None, None, None, None, None, None) == B.PDFX_EINVAL
     assert L.pdfx_eval_xfx_alphas(None, None, 0, None, 1, None, None, 10, None, None, 0,
                                   None) == B.PDFX_EINVAL
-    assert L.pdfx_bench_lds(4, 8, 8, 1024, None) == B.PDFX_EINVAL
+    assert L.pdfx_bench_lds(6, 8, 8, 1024, None) == B.PDFX_EINVAL
     assert L.pdfx_bench_lds(-1, 8, 8, 1024, None) == B.PDFX_EINVAL
     assert L.pdfx_bench_lds(0, 0, 8, 1024, None) == B.PDFX_EINVAL
     assert L.pdfx_bench_lds(1, 8, 8, None, None) == B.PDFX_EINVAL
