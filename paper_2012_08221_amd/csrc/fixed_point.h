@@ -31,13 +31,16 @@ __device__ __forceinline__ unsigned long long to_fixed(double c, double f)
 }
 
 // Fixed-point exponent for terms bounded by bnd, summed at most n at a time.
+// Kept within [-1000, 1000], so that 2^S and 2^-S are normal doubles; bounds
+// below ~2^-950 then give terms that round to 0.
 __device__ __forceinline__ int fixed_exponent(double bnd, int64_t n)
 {
     int lc, lb;
     frexp((double)n, &lc);   // n < 2^lc
     frexp(bnd, &lb);         // bnd < 2^lb (0 for bnd = 0)
     const int smax = 61 - lc < 50 ? 61 - lc : 50;
-    return smax - lb;
+    const int e = smax - lb;
+    return e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
 }
 
 }  // namespace pdfx

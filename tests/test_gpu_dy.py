@@ -203,3 +203,31 @@ def test_integrand_backward_kernels_agree(pdf, api, torch, prec):
     b = gb.double().cpu().numpy()[perm]
     tol = 1e-12 if prec == "f64" else 1e-6
     np.testing.assert_allclose(a, b, rtol=tol, atol=tol * np.abs(a).max())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_integrand_backward_scale_range_and_nan(pdf, api, torch, prec):
+    """The pair pass keeps its knot sums in 64-bit fixed point with a scale
+    from a bound on its terms: a scale factor of 1e-200 or 1e200 scales the
+    gradient alone; a NaN scale makes the quark and antiquark rows NaN and
+    leaves the gluon row at zero."""
+    g = cfg0_grid()
+    u1, u2 = wl.dy_uniforms(6, 200_000)
+    dt = api.prec_dtype(prec)
+
+    def grad(scale):
+        gr = torch.zeros(g.xf.shape, dtype=dt, device="cuda")
+        api.dy_backward(pdf, u1, u2, gr, XMIN, S, scale, prec=prec)
+        return gr.double().cpu().numpy()
+
+    g0 = grad(1.0)
+    big = np.abs(g0).max()
+    tol = 1e-9 if prec == "f64" else 1e-6
+    s_range = (1e-200, 1e200) if prec == "f64" else (1e-30, 1e30)   # FP32 output range
+    for s in s_range:
+        np.testing.assert_allclose(grad(s) / s, g0, rtol=tol, atol=tol * big)
+    gn = grad(float("nan"))
+    rows = {int(p): f for f, p in enumerate(g.pids)}
+    for p in (1, 2, 3, 4, 5, -1, -2, -3, -4, -5):
+        assert np.isnan(gn[rows[p]]).all()
+    assert np.all(gn[rows[21]] == 0.0)

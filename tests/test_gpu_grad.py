@@ -245,3 +245,34 @@ def test_gradcheck_tiny_fp64(torch, mods, nx):
     qd = torch.as_tensor(qq, device="cuda").requires_grad_(True)
     f = lambda v_, x_, q_: ag.xfx(pdf, v_, [21, 1], x_, q_, prec="f64")  # noqa: E731
     assert torch.autograd.gradcheck(f, (v, xd, qd), eps=1e-7, atol=1e-6, rtol=1e-5)
+
+
+def test_knot_gradient_scale_range_and_nan(torch, mods):
+    """The knot sums are kept in 64-bit fixed point with a scale taken from
+    max |dL/dout|: scaling dL/dout by 1e-200 or 1e200 scales the gradient
+    alone, and a NaN in one column makes that flavour's gradient NaN and
+    leaves the others as they were."""
+    api, ag = mods
+    g = cfg0_grid()
+    pdf = api.mkPDF(g, with_values=False)
+    n = 100_000
+    x, q2 = wl.queries(6, n)
+    w = wl.loss_weights(6, n)
+    xd, qd = torch.as_tensor(x, device="cuda"), torch.as_tensor(q2, device="cuda")
+
+    def grad(wn):
+        vals = torch.as_tensor(g.xf, device="cuda").requires_grad_(True)
+        (ag.xfx(pdf, vals, g.pids, xd, qd, prec="f64") * torch.as_tensor(wn, device="cuda")).sum().backward()
+        return vals.grad.cpu().numpy()
+
+    g0 = grad(w)
+    big = np.abs(g0).max()
+    for s in (1e-200, 1e200):
+        gs = grad(w * s)
+        np.testing.assert_allclose(gs / s, g0, rtol=1e-9, atol=1e-9 * big)
+    wn = w.copy()
+    wn[1234, 3] = np.nan
+    gn = grad(wn)
+    assert np.isnan(gn[3]).all()
+    keep = [f for f in range(g0.shape[0]) if f != 3]
+    np.testing.assert_allclose(gn[keep], g0[keep], rtol=1e-12, atol=1e-12 * big)
