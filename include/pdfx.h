@@ -166,12 +166,13 @@ int pdfx_eval_xfx_alphas(const pdfx_grid *g, const void *xf_dev, int prec,
  *           sum_r grad_out[p][r] * dout[p][r]/dx (resp. /dQ^2); NULL = skip.
  * Points outside the grid (NaN mode) contribute nothing and get NaN in
  * grad_x/grad_q2; in CLAMP mode the derivative along a clamped axis is 0.
- * The knot gradient is summed per workgroup in 64-bit fixed point (exact,
+ * On grids of up to 5000 knots the knot gradient is summed per workgroup
+ * in 64-bit fixed point (exact,
  * with a power-of-two scale taken from max |grad_out| over the workgroup's
  * points: resolution about 2^-44 of that bound at 1e7 points), then added
  * across workgroups with FP64 device atomics, so results are reproducible up
- * to the FP64 order of those sums.  A non-finite grad_out value makes its
- * flavour's whole knot gradient NaN. */
+ * to the FP64 order of those sums; there a non-finite grad_out value makes
+ * its flavour's whole knot gradient NaN.  Larger grids sum with FP64 atomics. */
 int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
                            const int32_t *pids, int32_t n_req,
                            const double *x, const double *q2, int64_t n_pts,
@@ -214,9 +215,10 @@ int32_t pdfx_dy_max_blocks(void);
 /* Backward of sum_p I[p] with respect to the PDF knot values:
  * grad_xf (device [n_flav][n_x][n_q], precision's type) += d(sum_p I[p]) / dv,
  * scaled by `scale` (e.g. 1/n for a mean).  alpha_s knots are not differentiated.
- * The knot sums are kept in 64-bit fixed point per workgroup (as for
- * pdfx_eval_xfx_backward); a non-finite scale or value makes the quark and
- * antiquark rows NaN. */
+ * With the 11 partons in the standard order the knot sums are kept in 64-bit
+ * fixed point per workgroup (as for pdfx_eval_xfx_backward), and a non-finite
+ * scale or value makes the quark and antiquark rows NaN; otherwise they are
+ * FP64 atomics. */
 int pdfx_eval_dy_backward(const pdfx_grid *g, const void *xf_dev, int prec,
                           const double *u1, const double *u2, int64_t n,
                           double xmin, double s, double scale, void *grad_xf,
