@@ -166,13 +166,13 @@ int pdfx_eval_xfx_alphas(const pdfx_grid *g, const void *xf_dev, int prec,
  *           sum_r grad_out[p][r] * dout[p][r]/dx (resp. /dQ^2); NULL = skip.
  * Points outside the grid (NaN mode) contribute nothing and get NaN in
  * grad_x/grad_q2; in CLAMP mode the derivative along a clamped axis is 0.
- * On grids of up to 5000 knots the knot gradient is summed per workgroup
- * in 64-bit fixed point (exact,
- * with a power-of-two scale taken from max |grad_out| over the workgroup's
- * points: resolution about 2^-44 of that bound at 1e7 points), then added
- * across workgroups with FP64 device atomics, so results are reproducible up
- * to the FP64 order of those sums; there a non-finite grad_out value makes
- * its flavour's whole knot gradient NaN.  Larger grids sum with FP64 atomics. */
+ * On grids of up to 5000 knots the knot gradient is summed per workgroup in
+ * 64-bit fixed point (exact, with a power-of-two scale from a bound on the
+ * terms that uses max |grad_out| over the workgroup's points: resolution
+ * about 2^-43 of that bound at 1e7 points), then added across workgroups
+ * with FP64 device atomics, so results are reproducible up to the FP64 order
+ * of those sums; there a non-finite grad_out value makes its flavour's whole
+ * knot gradient NaN.  Larger grids sum with FP64 atomics. */
 int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
                            const int32_t *pids, int32_t n_req,
                            const double *x, const double *q2, int64_t n_pts,
