@@ -207,17 +207,22 @@ __global__ __launch_bounds__(256) void dy_state_kernel(const DyArgs a)
     const double *asv = reinterpret_cast<const double *>(sm + a.lds_asv);
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < a.n;
          p += (int64_t)gridDim.x * 256) {
-        double x1 = exp(a.lnxmin + a.u1[p] * a.lnrange);
-        double x2 = exp(a.lnxmin + a.u2[p] * a.lnrange);
+        // ln x is the exponent itself (the bins compare raw x, so a last-bit
+        // difference from log(x) cannot change them)
+        double lnx1 = a.lnxmin + a.u1[p] * a.lnrange;
+        double lnx2 = a.lnxmin + a.u2[p] * a.lnrange;
+        double x1 = exp(lnx1);
+        double x2 = exp(lnx2);
         double q2 = x1 * x2 * a.s;
         q2 = q2 < a.aq.lo ? a.aq.lo : (q2 > a.aq.hi ? a.aq.hi : q2);
         const bool ok = x1 >= a.ax.lo && x1 <= a.ax.hi && x2 >= a.ax.lo && x2 <= a.ax.hi &&
                         q2 >= a.aa.lo && q2 <= a.aa.hi;
         if (!ok) {
             x1 = x2 = a.ax.lo;
+            lnx1 = lnx2 = a.ax.ln_lo;
             q2 = a.aq.lo > a.aa.lo ? a.aq.lo : a.aa.lo;
         }
-        const double lnx1 = log(x1), lnx2 = log(x2), lnq = log(q2);
+        const double lnq = log(q2);
         const int i1 = fwd::lbin(lx, x1, lnx1);
         const int i2 = fwd::lbin(lx, x2, lnx2);
         const int kq = fwd::lbin(lq, q2, lnq);
