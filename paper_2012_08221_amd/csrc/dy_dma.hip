@@ -100,11 +100,15 @@ __global__ __launch_bounds__(BLOCK) void dy_dma_kernel(const DyArgs a)
         st.ok = x1 >= a.ax.lo && x1 <= a.ax.hi && x2 >= a.ax.lo && x2 <= a.ax.hi &&
                 q2 >= a.aa.lo && q2 <= a.aa.hi;
         fwd::count_flagged(p < a.n && !st.ok, a.dom_count);
+        // ln x is the exponent itself (the bins compare raw x, so a last-bit
+        // difference from log(x) cannot change them)
+        double lnx1 = l1, lnx2 = l2;
         if (!st.ok) {
             x1 = x2 = a.ax.lo;
+            lnx1 = lnx2 = a.ax.ln_lo;
             q2 = a.aq.lo > a.aa.lo ? a.aq.lo : a.aa.lo;
         }
-        const double lnx1 = log(x1), lnx2 = log(x2), lnq = log(q2);
+        const double lnq = log(q2);
         const int i1 = fwd::lbin(lx, x1, lnx1);
         const int i2 = fwd::lbin(lx, x2, lnx2);
         const int kq = fwd::lbin(lq, q2, lnq);
