@@ -251,6 +251,24 @@ def main():
             print(json.dumps({"only": "xfx", "prec": args.prec, "xfx_ms": r["xfx_ms"]}))
             return
 
+        # latency of one call at the small size (1e5 points x 11 flavours and
+        # alpha_s, the parity configuration): mean over 200 back-to-back calls
+        if args.only is None and not args.no_extra:
+            xs_np, qs_np = wl.queries(0, 100_000)
+            xs = torch.as_tensor(xs_np, device=dev)
+            qs = torch.as_tensor(qs_np, device=dev)
+            lat = {"n_points": 100_000}
+            for prec in ("f64", "f32s"):
+                dt = api.prec_dtype(prec)
+                o = torch.empty((100_000, nf), dtype=dt, device=dev)
+                oa = torch.empty(100_000, dtype=dt, device=dev)
+                lat[prec + "_ms"] = timed(
+                    lambda: pdf.xfx_alphasQ2(pids, xs, qs, prec=prec, out=o, as_out=oa), 200, 5)
+            variants["latency_1e5"] = lat
+            log("1e5 points: %.1f us FP64, %.1f us FP32 per call"
+                % (lat["f64_ms"] * 1e3, lat["f32s_ms"] * 1e3))
+            del xs, qs, o, oa
+
         # EXTRAPOLATE mode on the same points with 1% of them moved below the
         # grid's x range (one decade): the forward pass plus the continuation
         if args.only is None and not args.no_extra:

@@ -233,7 +233,11 @@ int pdfx_eval_dy_backward(const pdfx_grid *g, const void *xf_dev, int prec,
 int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pts, const char *cache_path);
 int pdfx_autotune_set(pdfx_set *s, int prec, int32_t n_req, int64_t n_pts, const char *cache_path);
 
-/* Current launch shape of a grid: workgroup size and points per thread. */
+/* Current launch shape of a grid: workgroup size and points per thread.
+ * A default or tuned shape with ppt > 1 gives way to (512, 1) in a forward
+ * call whose points fill fewer workgroups than half the compute units (e.g.
+ * 1e5 points): smaller tiles keep more compute units busy.  A shape set by
+ * pdfx_set_launch is used at every size. */
 int pdfx_get_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
 /* Forces a launch shape (must be one of the compiled ones): ppt > 0 holds
  * results in registers ((256, 2), (256, 4), (512, 1), (512, 2), (1024, 1),

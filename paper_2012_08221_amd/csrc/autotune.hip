@@ -181,6 +181,7 @@ extern "C" int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pt
     if (ce.found && (launch_shape_supported(cached) ||
                      (prec == PDFX_F32S && launch_shape_f32_only(cached)))) {
         g->shape[prec] = cached;
+        g->shape_pinned[prec] = false;
         return PDFX_OK;
     }
     const int64_t n = n_pts < (1LL << 23) ? n_pts : (1LL << 23);
@@ -199,6 +200,7 @@ extern "C" int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pt
         cand.push_back(launch_shape_at(i));
     if (prec == PDFX_F32S)
         cand.push_back(LaunchShape{512, 4});
+    g->shape_pinned[prec] = true;   // each candidate runs as it is
     for (const LaunchShape ls : cand) {
         g->shape[prec] = ls;
         g->reset_occupancy(prec);
@@ -214,6 +216,7 @@ extern "C" int pdfx_autotune(pdfx_grid *g, int prec, int32_t n_req, int64_t n_pt
         }
     }
     g->shape[prec] = best_ls;
+    g->shape_pinned[prec] = false;
     g->reset_occupancy(prec);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess)

@@ -496,6 +496,7 @@ int pdfx_set_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
         return fail(PDFX_EINVAL, "launch shape (%d, %d) not compiled for this precision", block,
                     ppt);
     g->shape[prec] = ls;
+    g->shape_pinned[prec] = true;
     return PDFX_OK;
 }
 
@@ -865,6 +866,12 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
     if (as_done)
         *as_done = false;
     LaunchShape ls = g->shape[prec];
+    if (!g->shape_pinned[prec] && ls.ppt > 1) {
+        // a small call: (512, 1) gives twice or more the workgroups
+        const int64_t tile = (int64_t)ls.block * ls.ppt;
+        if ((a.n + tile - 1) / tile < g->cus / 2)
+            ls = LaunchShape{512, 1};
+    }
     const bool staged = ls.ppt > 0 && plan_stages(a, f32 ? 4 : 2);
     if (staged && g->dma_grid && (uintptr_t)a.out % 16 == 0 &&
         dma_supported(ls, a.nx, a.nq, a.ax.nbuckets, a.aq.nbuckets, f32)) {

@@ -74,6 +74,10 @@ struct pdfx_grid {
     pdfx::DeviceBuf as_vals64, as_vals32;    // padded [n_as + 2]
     pdfx::DeviceBuf dom_count;               // unsigned long long
     pdfx::LaunchShape shape[2];              // per precision
+    // shape[prec] set by pdfx_set_launch: used as it is at every size (a tuned
+    // or default shape gives way to (512, 1) when a call has too few points
+    // to give every other compute unit a tile)
+    bool shape_pinned[2] = {false, false};
     pdfx::LaunchShape dy_shape[2] = {{512, 1}, {512, 2}};   // double-buffered integrand kernel
     pdfx::LaunchShape lumi_shape[2] = {{512, 2}, {512, 2}};  // flavour-pair luminosity kernel
     mutable pdfx::DeviceBuf bwd_ws;          // adjoint workspace (grows on demand)
