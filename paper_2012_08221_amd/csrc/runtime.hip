@@ -934,14 +934,15 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
 
 }  // namespace pdfx
 
-// Resident workgroups of the current launch shape over the whole device
-// (cached per precision and kernel; the persistent kernels never launch more).
+// Resident workgroups of launch shape ls over the whole device (cached per
+// precision, kernel and shape; the persistent kernels never launch more).
 int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a, int kernel,
                           pdfx::LaunchShape ls) const
 {
-    if (occ_shape[prec][kernel].block == ls.block && occ_shape[prec][kernel].ppt == ls.ppt &&
-        occ_blocks[prec][kernel] > 0)
-        return occ_blocks[prec][kernel];
+    for (int c = 0; c < 2; ++c)
+        if (occ_shape[prec][kernel][c].block == ls.block &&
+            occ_shape[prec][kernel][c].ppt == ls.ppt && occ_blocks[prec][kernel][c] > 0)
+            return occ_blocks[prec][kernel][c];
     int per_cu = 0;
     hipError_t e;
     if (kernel == 2)
@@ -955,9 +956,11 @@ int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a, int kernel,
                               : pdfx::xfx_occupancy_f64(a, ls, &per_cu);
     if (e != hipSuccess || per_cu < 1)
         per_cu = 1;
-    occ_shape[prec][kernel] = ls;
-    occ_blocks[prec][kernel] = per_cu * cus;
-    return occ_blocks[prec][kernel];
+    const int c = occ_next[prec][kernel];
+    occ_next[prec][kernel] = c ^ 1;
+    occ_shape[prec][kernel][c] = ls;
+    occ_blocks[prec][kernel][c] = per_cu * cus;
+    return occ_blocks[prec][kernel][c];
 }
 
 // ---------------------------------------------------------------------------

@@ -81,12 +81,19 @@ struct pdfx_grid {
     pdfx::LaunchShape dy_shape[2] = {{512, 1}, {512, 2}};   // double-buffered integrand kernel
     pdfx::LaunchShape lumi_shape[2] = {{512, 2}, {512, 2}};  // flavour-pair luminosity kernel
     mutable pdfx::DeviceBuf bwd_ws;          // adjoint workspace (grows on demand)
-    // resident-workgroup cache per [precision][kernel: per-flavour, grouped, double-buffered]
-    mutable pdfx::LaunchShape occ_shape[2][3] = {};
-    mutable int occ_blocks[2][3] = {};
+    // resident-workgroup cache per [precision][kernel: per-flavour, grouped,
+    // double-buffered], two shapes each (a grid's own shape and the one small
+    // calls take), the older entry replaced on a miss
+    mutable pdfx::LaunchShape occ_shape[2][3][2] = {};
+    mutable int occ_blocks[2][3][2] = {};
+    mutable int occ_next[2][3] = {};
     int row_of(int pid) const;
     int max_blocks(int prec, const pdfx::XfxArgs &a, int kernel, pdfx::LaunchShape ls) const;
-    void reset_occupancy(int prec) const { occ_blocks[prec][0] = occ_blocks[prec][1] = occ_blocks[prec][2] = 0; }
+    void reset_occupancy(int prec) const
+    {
+        for (int k = 0; k < 3; ++k)
+            occ_blocks[prec][k][0] = occ_blocks[prec][k][1] = 0;
+    }
 };
 
 namespace pdfx {

@@ -385,7 +385,7 @@ def test_xfx_alphas_other_paths(pdf0, torch, api):
         _, s = _fused_vs_separate(torch, pdf4, [21, -1], xs, qs, prec, "nan")
         ora = oracle.alphas(g4.as_q2, g4.as_val, qs)
         assert np.max(np.abs(s - ora) / np.abs(ora)) <= TOL[prec]
-    g2 = cfg0_grid()
+    g2 = wl.config0_grid()               # a fresh copy: its alpha_s knots change
     g2.as_q2 = np.geomspace(1.0, 1e10, 37)
     g2.as_val = 0.3 / (1.0 + 0.05 * np.log(g2.as_q2))
     pdf2 = api.mkPDF(g2)
@@ -401,10 +401,28 @@ def test_xfx_alphas_rejects(pdf0, torch, api):
     x = torch.full((8,), 0.1, dtype=torch.float64, device="cuda")
     with pytest.raises(B.PdfxError):
         pdf0.xfx_alphasQ2(list(g.pids), x, x * 100, domain="extrapolate")
-    g3 = cfg0_grid()
+    g3 = wl.config0_grid()               # a fresh copy: its alpha_s knots go
     g3.as_q2 = np.zeros(0)
     g3.as_val = np.zeros(0)
     pdf3 = api.mkPDF(g3)
     with pytest.raises(B.PdfxError) as e:
         pdf3.xfx_alphasQ2(list(g.pids), x, x * 100)
     assert e.value.code == B.PDFX_ENOALPHAS
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_small_calls_switch_shape_bitwise(api, torch, prec):
+    """A grid's default shape gives way to (512, 1) for calls too small to
+    fill the device; calls of both sizes, alternating, give the bits of the
+    same calls on a grid whose shape was set explicitly."""
+    g = cfg0_grid()
+    auto = api.mkPDF(g)
+    pinned = api.mkPDF(g)
+    pinned.set_launch(prec, *auto.launch(prec))
+    for n in (100_000, 2_000_003, 777, 100_000):
+        x, q2 = wl.queries(40 + n % 7, n)
+        xd, qd = torch.as_tensor(x, device="cuda"), torch.as_tensor(q2, device="cuda")
+        a, aa = auto.xfx_alphasQ2(g.pids, xd, qd, prec=prec)
+        b, ba = pinned.xfx_alphasQ2(g.pids, xd, qd, prec=prec)
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+        np.testing.assert_array_equal(aa.cpu().numpy(), ba.cpu().numpy())
