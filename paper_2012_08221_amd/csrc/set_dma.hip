@@ -160,7 +160,7 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
             const int64_t t0 = tile * tile_pts;
             const bool more = tile + 1 < t_end;
             if (SPLIT && tile > t_first && n_stage > 0) {
-                __syncthreads();   // the previous tile's output rows have left slab1
+                __syncthreads();   // the previous tile's output rows have left both slabs
                 load_group(a.sgrp[0]);
             }
             V wx[PPT][4], wq[PPT][4];
@@ -253,19 +253,33 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
                 }
             }
 
-            // output rows, assembled in slab1 and written as 16-byte chunks
+            // Output rows, assembled in both slabs (rows [0, cap) of a pass in
+            // slab1, the next cap in slab0; cap is a multiple of 16 rows) and
+            // written as 16-byte chunks, slab0's part first: on the last pass
+            // the next tile's first group then goes into slab0 while slab1's
+            // part is written.
             __syncthreads();   // every stencil read is done
             const int valid = (int)(a.n - t0 < tile_pts ? a.n - t0 : tile_pts);
-            V *lrow = reinterpret_cast<V *>(slab1);
-            for (int pa = 0; pa < valid; pa += a.out_pass_pts) {
-                const int pn = valid - pa < a.out_pass_pts ? valid - pa : a.out_pass_pts;
+            const int cap = a.out_pass_pts;
+            const int rb = n_req * (int)sizeof(V);
+            auto write_rows = [&](const uint4 *src, char *dst, int bytes) {
+                const int nch = bytes >> 4;
+                for (int c = tid; c < nch; c += BLOCK)
+                    *reinterpret_cast<uint4 *>(dst + c * 16) = src[c];
+                if (tid < (bytes & 15) / 4)
+                    reinterpret_cast<uint32_t *>(dst + nch * 16)[tid] =
+                        reinterpret_cast<const uint32_t *>(src + nch)[tid];
+            };
+            for (int pa = 0; pa < valid; pa += 2 * cap) {
+                const int pn = valid - pa < 2 * cap ? valid - pa : 2 * cap;
                 if (pa > 0)
                     __syncthreads();   // the previous pass has left LDS
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
                     const int lp = tid + j * BLOCK - pa;
                     if (lp >= 0 && lp < pn) {
-                        V *r = lrow + lp * n_req;
+                        V *r = reinterpret_cast<V *>(lp < cap ? slab1 : slab0) +
+                               (lp < cap ? lp : lp - cap) * n_req;
 #pragma unroll
                         for (int k = 0; k < NSG; ++k)
                             if (k < n_stage * G && a.slot_col[k] >= 0)
@@ -277,16 +291,16 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
                     }
                 }
                 __syncthreads();
-                if (!SPLIT && pa + a.out_pass_pts >= valid && n_stage > 1 && more)
-                    fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);
-                const int bytes = pn * n_req * (int)sizeof(V);
+                const int n1 = pn < cap ? pn : cap;   // rows in slab1; pn - n1 in slab0
                 char *dst = reinterpret_cast<char *>(out + (t0 + pa) * n_req);   // 16-byte aligned
-                const int nch = bytes >> 4;
-                for (int c = tid; c < nch; c += BLOCK)
-                    *reinterpret_cast<uint4 *>(dst + c * 16) = slab1[c];
-                if (tid < (bytes & 15) / 4)
-                    reinterpret_cast<uint32_t *>(dst + nch * 16)[tid] =
-                        reinterpret_cast<const uint32_t *>(slab1 + nch)[tid];
+                if (pn > n1)
+                    write_rows(slab0, dst + n1 * rb, (pn - n1) * rb);
+                if (!SPLIT && pa + 2 * cap >= valid && n_stage > 1 && more) {
+                    if (pn > n1)
+                        __syncthreads();   // slab0's rows are read
+                    fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);
+                }
+                write_rows(slab1, dst, n1 * rb);
             }
         }
     }
