@@ -359,7 +359,7 @@ def test_xfx_alphas_one_call(pdf0, torch, prec, domain):
 def test_xfx_alphas_other_paths(pdf0, torch, api):
     """The two-pass fallbacks: an output that only the other kernels take
     (8-byte aligned, not 16), a request order with repeats, and a grid whose
-    alpha_s knots are not its Q^2 knots."""
+    alpha_s knots are not its Q^2 knots; and caller-provided values."""
     g = cfg0_grid()
     x, q2 = cfg0_queries(20_000)
     n = len(x)
@@ -370,6 +370,8 @@ def test_xfx_alphas_other_paths(pdf0, torch, api):
         out = buf[off:off + n * 3].view(n, 3)
         assert out.data_ptr() % 16 == 8
         _fused_vs_separate(torch, pdf0, [2, 21, 2], x, q2, prec, "nan", out=out)
+        vals = torch.as_tensor(g.xf, device="cuda").to(dt)   # caller-provided values
+        _fused_vs_separate(torch, pdf0, list(g.pids), x, q2, prec, "clamp", values=vals)
     # 200 x 25 knots: alpha_s values fit the double-buffered kernel's LDS
     # in FP32 (one pass) but not in FP64 (two passes)
     rng = np.random.default_rng(7)
