@@ -281,7 +281,9 @@ int pdfx_eval_lumi(const pdfx_grid *g, const void *xf_dev, int prec, int32_t n_p
                    int64_t n, void *out_pair, void *out_sum, int domain_mode, void *stream);
 
 /* Launch shape of the luminosity kernel per precision (default (512, 2));
- * compiled: (512, 1), (512, 2), (256, 2), and (512, 4) for PDFX_F32S. */
+ * compiled: (512, 1), (512, 2), (256, 2), and (512, 4) for PDFX_F32S.  As for
+ * pdfx_get_launch, the default gives way to (512, 1) in a call too small to
+ * give half the compute units a tile; a shape set here is used at every size. */
 int pdfx_get_lumi_launch(const pdfx_grid *g, int prec, int32_t *block, int32_t *ppt);
 int pdfx_set_lumi_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 

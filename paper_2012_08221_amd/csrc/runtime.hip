@@ -549,6 +549,7 @@ int pdfx_set_lumi_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt)
     if (!lumi_shape_supported(ls, prec == PDFX_F32S))
         return fail(PDFX_EINVAL, "luminosity launch shape (%d, %d) not compiled", block, ppt);
     g->lumi_shape[prec] = ls;
+    g->lumi_pinned[prec] = true;
     return PDFX_OK;
 }
 
@@ -1711,7 +1712,14 @@ int pdfx_eval_lumi(const pdfx_grid *g, const void *xf_dev, int prec, int32_t n_p
     a.out_sum = out_sum;
     a.domain_mode = domain_mode;
     a.dom_count = (unsigned long long *)g->dom_count.ptr;
-    if ((e = launch_lumi(a, f32, g->lumi_shape[prec], g->cus, (hipStream_t)stream)) != hipSuccess)
+    LaunchShape ls = g->lumi_shape[prec];
+    if (!g->lumi_pinned[prec] && ls.ppt > 1) {
+        // a small call: (512, 1) gives twice or more the workgroups
+        const int64_t tile = (int64_t)ls.block * ls.ppt;
+        if ((n + tile - 1) / tile < g->cus / 2)
+            ls = LaunchShape{512, 1};
+    }
+    if ((e = launch_lumi(a, f32, ls, g->cus, (hipStream_t)stream)) != hipSuccess)
         return fail_hip(e, "luminosity launch");
     return PDFX_OK;
 }

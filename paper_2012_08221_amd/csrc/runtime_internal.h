@@ -80,6 +80,7 @@ struct pdfx_grid {
     bool shape_pinned[2] = {false, false};
     pdfx::LaunchShape dy_shape[2] = {{512, 1}, {512, 2}};   // double-buffered integrand kernel
     pdfx::LaunchShape lumi_shape[2] = {{512, 2}, {512, 2}};  // flavour-pair luminosity kernel
+    bool lumi_pinned[2] = {false, false};    // lumi_shape set by pdfx_set_lumi_launch
     mutable pdfx::DeviceBuf bwd_ws;          // adjoint workspace (grows on demand)
     // resident-workgroup cache per [precision][kernel: per-flavour, grouped,
     // double-buffered], two shapes each (a grid's own shape and the one small

@@ -162,3 +162,20 @@ def test_caller_values_and_empty(pdf, grid, torch):
                        with_alphas=False)
     with pytest.raises(PdfxError, match="luminosity kernel"):
         api.mkPDF(big).lumi(*SINGLE_TOP, x1, x2, q2_fixed=MT2)
+
+
+def test_small_calls_default_shape(torch, grid):
+    """A default-shape grid runs small calls as (512, 1); their bits equal
+    those of a grid whose shape was set, at small and large sizes."""
+    from paper_2012_08221_amd import api
+    auto = api.mkPDF(grid)
+    pinned = api.mkPDF(grid)
+    pa, pb = [5, 5, 21], [2, -1, 21]
+    for prec in ("f64", "f32s"):
+        pinned.set_lumi_launch(prec, *auto.lumi_launch(prec))
+        for n in (5_000, 600_001, 5_000):
+            x1, x2, q2 = points(7, n)
+            a = auto.lumi(pa, pb, x1, x2, q2=q2, prec=prec)
+            b = pinned.lumi(pa, pb, x1, x2, q2=q2, prec=prec)
+            for u, v in zip(a, b):
+                np.testing.assert_array_equal(u.cpu().numpy(), v.cpu().numpy())
