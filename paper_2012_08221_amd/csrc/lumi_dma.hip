@@ -32,7 +32,10 @@ struct LumiPoint {
     bool ok;
 };
 
-template <typename V, int BLOCK, int PPT>
+// FQ: one Q^2 for every point (q2 null).  The Q^2 location (log, bin,
+// weights, window) is then found once per thread and shared by the points,
+// with the same arithmetic as per point, so the results are the same bits.
+template <typename V, int BLOCK, int PPT, bool FQ>
 __global__ __launch_bounds__(BLOCK) void lumi_kernel(const LumiArgs a)
 {
     constexpr int G = 16 / (int)sizeof(V);
@@ -86,9 +89,50 @@ __global__ __launch_bounds__(BLOCK) void lumi_kernel(const LumiArgs a)
     const double q2_fixed = a.q2_fixed;
     const bool q2_arr = a.q2 != nullptr;
 
+    // The fixed Q^2's location: inside, clamped into the grid (CLAMP mode),
+    // or, when every point is outside (NaN mode), the first knot.
+    V wqf[4];
+    int cqf = 0;
+    bool q_in = true;
+    if constexpr (FQ) {
+        double q2 = q2_fixed;
+        q_in = q2 >= a.aq.lo && q2 <= a.aq.hi;
+        if (!q_in)
+            q2 = a.domain_mode == 1 ? fmin(fmax(q2, a.aq.lo), a.aq.hi) : a.aq.lo;
+        const double lnq = log(q2);
+        const int kq = fwd::lbin(lq, q2, lnq);
+        fwd::weights_gmem<V>(a.aq, kq, lnq, wqf);
+        cqf = fwd::window(kq, nq, wqf);
+    }
+
     // Domain rule of the forward evaluation applied to x1, x2 and Q^2
     // together; logs, bins, weights and windows of both points.
     auto locate = [&](int64_t p, double x1, double x2, double q2, LumiPoint<V> &st) {
+        if constexpr (FQ) {
+            const bool nan_in = (x1 != x1) || (x2 != x2);
+            const bool inside = x1 >= a.ax.lo && x1 <= a.ax.hi && x2 >= a.ax.lo &&
+                                x2 <= a.ax.hi && q_in;
+            st.ok = true;
+            if (!inside) {
+                if (a.domain_mode == 1 && !nan_in) {
+                    x1 = fmin(fmax(x1, a.ax.lo), a.ax.hi);
+                    x2 = fmin(fmax(x2, a.ax.lo), a.ax.hi);
+                } else {
+                    st.ok = false;
+                    x1 = x2 = a.ax.lo;
+                }
+            }
+            fwd::count_flagged(p < a.n && !st.ok, a.dom_count);
+            const double lnx1 = log(x1), lnx2 = log(x2);
+            const int i1 = fwd::lbin(lx, x1, lnx1);
+            const int i2 = fwd::lbin(lx, x2, lnx2);
+            fwd::weights_gmem<V>(a.ax, i1, lnx1, st.w1);
+            fwd::weights_gmem<V>(a.ax, i2, lnx2, st.w2);
+            st.b1 = fwd::window(i1, nx, st.w1) * nq + cqf;
+            st.b2 = fwd::window(i2, nx, st.w2) * nq + cqf;
+            st.inv = (V)(1.0 / (x1 * x2));
+            return;
+        }
         const bool nan_in = (x1 != x1) || (x2 != x2) || (q2 != q2);
         const bool inside = x1 >= a.ax.lo && x1 <= a.ax.hi && x2 >= a.ax.lo && x2 <= a.ax.hi &&
                             q2 >= a.aq.lo && q2 <= a.aq.hi;
@@ -186,14 +230,14 @@ __global__ __launch_bounds__(BLOCK) void lumi_kernel(const LumiArgs a)
                 for (int j = 0; j < PPT; ++j) {
                     if (sd & 1) {
                         V t[G];
-                        stencil(cur, pt[j].b1, pt[j].w1, pt[j].wq, t);
+                        stencil(cur, pt[j].b1, pt[j].w1, FQ ? wqf : pt[j].wq, t);
 #pragma unroll
                         for (int g = 0; g < G; ++g)
                             r1[j][s * G + g] = t[g];
                     }
                     if (sd & 2) {
                         V t[G];
-                        stencil(cur, pt[j].b2, pt[j].w2, pt[j].wq, t);
+                        stencil(cur, pt[j].b2, pt[j].w2, FQ ? wqf : pt[j].wq, t);
 #pragma unroll
                         for (int g = 0; g < G; ++g)
                             r2[j][s * G + g] = t[g];
@@ -262,15 +306,17 @@ hipError_t launch_typed(const LumiArgs &a, LaunchShape ls, int cus, hipStream_t 
         hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), 0, s, a);
         return hipGetLastError();
     };
+    const bool fq = a.q2 == nullptr;
     if (ls.block == 512 && ls.ppt == 1)
-        return go(lumi_kernel<V, 512, 1>, 512, 1);
+        return fq ? go(lumi_kernel<V, 512, 1, true>, 512, 1) : go(lumi_kernel<V, 512, 1, false>, 512, 1);
     if (ls.block == 512 && ls.ppt == 2)
-        return go(lumi_kernel<V, 512, 2>, 512, 2);
+        return fq ? go(lumi_kernel<V, 512, 2, true>, 512, 2) : go(lumi_kernel<V, 512, 2, false>, 512, 2);
     if (ls.block == 256 && ls.ppt == 2)
-        return go(lumi_kernel<V, 256, 2>, 256, 2);
+        return fq ? go(lumi_kernel<V, 256, 2, true>, 256, 2) : go(lumi_kernel<V, 256, 2, false>, 256, 2);
     if constexpr (sizeof(V) == 4) {
         if (ls.block == 512 && ls.ppt == 4)
-            return go(lumi_kernel<V, 512, 4>, 512, 4);
+            return fq ? go(lumi_kernel<V, 512, 4, true>, 512, 4)
+                      : go(lumi_kernel<V, 512, 4, false>, 512, 4);
     }
     return hipErrorInvalidValue;
 }

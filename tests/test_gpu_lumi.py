@@ -179,3 +179,29 @@ def test_small_calls_default_shape(torch, grid):
             b = pinned.lumi(pa, pb, x1, x2, q2=q2, prec=prec)
             for u, v in zip(a, b):
                 np.testing.assert_array_equal(u.cpu().numpy(), v.cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+@pytest.mark.parametrize("domain", ["nan", "clamp"])
+def test_fixed_q2_matches_per_point_array(pdf, grid, torch, prec, domain):
+    """With one Q^2 for all points the kernel locates Q^2 once; the bits equal
+    those of the same Q^2 given per point, with points outside in x, NaN x, a
+    Q^2 inside, on a threshold knot and outside the grid, in every shape."""
+    x1, x2, _ = points(9, 20_003)
+    x1[::101] = 1e-11
+    x2[5::211] = 2.0
+    x1[7::307] = np.nan
+    pa, pb = [5, 5, 5, 5, 21], [2, 4, -1, -3, 21]
+    keep = pdf.lumi_launch(prec)
+    try:
+        for qf in (172.5 ** 2, float(grid.q2[grid.q_off[2]]), 0.25, 3e10):
+            qa = np.full(x1.size, qf)
+            for shape in ((512, 1), (512, 2), (256, 2)) + (((512, 4),) if prec == "f32s" else ()):
+                pdf.set_lumi_launch(prec, *shape)
+                a = pdf.lumi(pa, pb, x1, x2, q2_fixed=qf, prec=prec, domain=domain)
+                b = pdf.lumi(pa, pb, x1, x2, q2=qa, prec=prec, domain=domain)
+                for u, v in zip(a, b):
+                    np.testing.assert_array_equal(u.cpu().numpy(), v.cpu().numpy())
+    finally:
+        pdf.set_lumi_launch(prec, *keep)
+
