@@ -64,12 +64,10 @@ __device__ __forceinline__ double cont(double fe, double fn, double u)
     return fe + u * (fn - fe);
 }
 
-// True if point p is outside the grid (and no coordinate is NaN: such a
-// point keeps the forward pass's NaN).
-__device__ __forceinline__ bool outside(const ExtrapArgs &a, int64_t p)
+// True if a point with coordinates (xv, qv) is outside the grid (and no
+// coordinate is NaN: such a point keeps the forward pass's NaN).
+__device__ __forceinline__ bool outside(const ExtrapArgs &a, double xv, double qv)
 {
-    const double xv = a.x[p];
-    double qv = a.q[p];
     if (a.q_is_q)
         qv = qv * qv;
     if (xv != xv || qv != qv)
@@ -77,9 +75,9 @@ __device__ __forceinline__ bool outside(const ExtrapArgs &a, int64_t p)
     return xv < a.ax.lo || xv > a.ax.hi || qv < a.aq.lo || qv > a.aq.hi;
 }
 
-// The continuation of one point outside the grid, every output column.
+// The continuation of one point outside the grid, output column r.
 template <typename V>
-__device__ void continue_point(const ExtrapArgs &a, int64_t p)
+__device__ void continue_column(const ExtrapArgs &a, int64_t p, int r)
 {
     V *out = reinterpret_cast<V *>(a.out);
     const int ld = a.nq + 2;   // bordered slab: knot (i, k) at (i + 1) * ld + k + 1
@@ -110,8 +108,7 @@ __device__ void continue_point(const ExtrapArgs &a, int64_t p)
             weights64(a.ax, bin, xv, lx, w);
         }
         V *o = out + p * a.n_req;
-#pragma unroll 4
-        for (int r = 0; r < a.n_req; ++r) {
+        {
             const int row = a.row[r];
             double v = 0.0;
             if (row >= 0) {
@@ -150,10 +147,12 @@ __device__ void continue_point(const ExtrapArgs &a, int64_t p)
 }
 
 // Each workgroup takes chunks of kExtrapChunk points: it lists the chunk's
-// outside points in LDS, then continues them with every lane busy (outside
-// points are few and scattered, so most waves would otherwise run the long
-// path for one lane).
+// outside points in LDS, then continues them one (point, column) per lane,
+// with every lane busy (outside points are few and scattered, so most waves
+// would otherwise run the long path for one lane; each column costs a log
+// and an exp, so columns in parallel shorten it further).
 constexpr int kExtrapChunk = 4096;
+static_assert(kExtrapChunk % kExtrapBlock == 0, "a chunk is whole rounds of the workgroup");
 
 template <typename V>
 __global__ __launch_bounds__(kExtrapBlock) void extrap_kernel(const ExtrapArgs a)
@@ -165,15 +164,26 @@ __global__ __launch_bounds__(kExtrapBlock) void extrap_kernel(const ExtrapArgs a
         if (threadIdx.x == 0)
             count = 0;
         __syncthreads();
-        for (int i = threadIdx.x; i < kExtrapChunk; i += kExtrapBlock) {
-            const int64_t p = c0 + i;
-            if (p < a.n && outside(a, p))
+        // all of the thread's coordinates first, so that their loads overlap
+        // (clamped indices keep them global loads)
+        constexpr int kPer = kExtrapChunk / kExtrapBlock;
+        double xs[kPer], qs[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t p = c0 + threadIdx.x + u * kExtrapBlock;
+            xs[u] = load_point(a.x, p, a.n);
+            qs[u] = load_point(a.q, p, a.n);
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int i = threadIdx.x + u * kExtrapBlock;
+            if (c0 + i < a.n && outside(a, xs[u], qs[u]))
                 list[atomicAdd(&count, 1)] = i;
         }
         __syncthreads();
         const int n_out = count;
-        for (int k = threadIdx.x; k < n_out; k += kExtrapBlock)
-            continue_point<V>(a, c0 + list[k]);
+        for (int k = threadIdx.x; k < n_out * a.n_req; k += kExtrapBlock)
+            continue_column<V>(a, c0 + list[k / a.n_req], k % a.n_req);
         __syncthreads();   // the list is read before the next chunk refills it
     }
 }
@@ -182,9 +192,9 @@ __global__ __launch_bounds__(kExtrapBlock) void extrap_kernel(const ExtrapArgs a
 
 hipError_t launch_extrap(const ExtrapArgs &a, bool f32, int cus, hipStream_t s)
 {
-    int64_t grid = (a.n + kExtrapChunk - 1) / kExtrapChunk;
-    if (grid > (int64_t)cus * 8)
-        grid = (int64_t)cus * 8;
+    int64_t grid = (a.n + kExtrapChunk - 1) / kExtrapChunk;   // one chunk per workgroup
+    if (grid > (int64_t)cus * 64)
+        grid = (int64_t)cus * 64;
     if (grid < 1)
         return hipSuccess;
     if (f32)
