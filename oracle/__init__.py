@@ -37,9 +37,15 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        _lib = ctypes.CDLL(_LIB)
+        # ORACLE_LIB_OVERRIDE: a library built from a deliberately altered copy
+        # of the source, used only by the test that checks that the pins catch
+        # planted mistakes
+        path = os.environ.get("ORACLE_LIB_OVERRIDE")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        _lib = ctypes.CDLL(path)
         d, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_long
         _lib.ora_xfx.argtypes = [i32, d, i32, d, i32, d, d, d, i32, d, i64, d, d, d, i32, i32]
         _lib.ora_locate.argtypes = [i32, d, i32, d, d, i64, d, d, d, d, d, d]

@@ -295,7 +295,9 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
                 char *dst = reinterpret_cast<char *>(out + (t0 + pa) * n_req);   // 16-byte aligned
                 if (pn > n1)
                     write_rows(slab0, dst + n1 * rb, (pn - n1) * rb);
-                if (!SPLIT && pa + 2 * cap >= valid && n_stage > 1 && more) {
+                // slab0 is re-filled when it held another group or output rows
+                if (!SPLIT && pa + 2 * cap >= valid && more &&
+                    (n_stage > 1 || (n_stage == 1 && valid > cap))) {
                     if (pn > n1)
                         __syncthreads();   // slab0's rows are read
                     fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);

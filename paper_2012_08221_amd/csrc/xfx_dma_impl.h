@@ -287,7 +287,8 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
         // other slab during stage s.  The next tile's first slab goes into
         // slab0 after the last barrier of the output phase (every barrier
         // also waits for the copies in flight), so that it lands during the
-        // output stores.  A lone group stays in slab0.
+        // output stores.  A lone group stays in slab0 unless output rows were
+        // staged over it.
         V res[PPT][NSG];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -359,7 +360,9 @@ __global__ __launch_bounds__(BLOCK) void xfx_dma_kernel(const XfxArgs a)
             char *dst = reinterpret_cast<char *>(out + (t0 + pa) * n_req);   // 16-byte aligned
             if (pn > n1)
                 write_rows(slab0, dst + n1 * rb, (pn - n1) * rb);
-            if (pa + 2 * cap >= valid && n_stage > 1 && more) {
+            // slab0 must be re-filled for the next tile when it held another
+            // group (n_stage > 1) or output rows of this tile (valid > cap)
+            if (pa + 2 * cap >= valid && more && (n_stage > 1 || (n_stage == 1 && valid > cap))) {
                 if (pn > n1)
                     __syncthreads();   // slab0's rows are read
                 dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * a.gstride, nodes);
