@@ -19,7 +19,7 @@
  *    The caller owns them and the stream; the library never frees them.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Every eval call
  *    only enqueues work on it and returns; nothing is copied to or from the
- *    host on the eval path.
+ *    host on the eval path (except in domain mode PDFX_DOMAIN_ERROR, below).
  *  - A failed call leaves every handle valid and enqueues nothing.
  *  - A grid (or set) owns scratch memory that its calls share: repacked
  *    caller values, the adjoint and integrand-gradient workspaces and the
@@ -45,6 +45,14 @@
  *    u = ln(z/z_e) / ln(z_n/z_e): xf = F_e (F_n/F_e)^u if F_n/F_e > 0, else
  *    F_e + u (F_n - F_e); outside in x and Q^2 alike, x first, then Q^2.
  *    It counts only NaN inputs.  The other calls reject it.
+ *    PDFX_DOMAIN_ERROR (every forward call: x f, alpha_s, both in one pass,
+ *    sets, luminosity) evaluates as PDFX_DOMAIN_NAN, then waits for the
+ *    stream and returns PDFX_EDOMAIN if any point of this call was outside
+ *    the grid or NaN (its outputs are written as in NAN mode and the points
+ *    are added to the pdfx_domain_errors / pdfx_set_domain_errors count).
+ *    It is the one synchronous evaluation mode: do not use it under HIP
+ *    graph capture.  pdfx_check_points applies the same rule to host arrays
+ *    before anything is uploaded.
  *  - Ties: a Q^2 equal to a subgrid threshold uses the upper subgrid; a
  *    query on the last knot of an axis uses the last interval.
  */
@@ -83,6 +91,9 @@ enum pdfx_status {
     PDFX_EINVAL = -1,     /* invalid argument or descriptor */
     PDFX_ENOMEM = -2,     /* device allocation failed */
     PDFX_EHIP = -3,       /* a HIP runtime call failed */
+    PDFX_EDOMAIN = -4,    /* a point outside the grid: returned only by PDFX_DOMAIN_ERROR
+                             calls (outputs written, NaN at those points) and by
+                             pdfx_check_points */
     PDFX_ENOALPHAS = -5,  /* the grid has no alpha_s knots */
     PDFX_ENOVALUES = -6   /* no owned values and none passed */
 };
@@ -94,7 +105,12 @@ enum pdfx_status {
  *            FMAs, values and outputs FP32. */
 enum pdfx_prec { PDFX_F64 = 0, PDFX_F32S = 1 };
 
-enum pdfx_domain { PDFX_DOMAIN_NAN = 0, PDFX_DOMAIN_CLAMP = 1, PDFX_DOMAIN_EXTRAPOLATE = 2 };
+enum pdfx_domain {
+    PDFX_DOMAIN_NAN = 0,
+    PDFX_DOMAIN_CLAMP = 1,
+    PDFX_DOMAIN_EXTRAPOLATE = 2,
+    PDFX_DOMAIN_ERROR = 3
+};
 
 /* Maximum number of requested pids in one call. */
 #define PDFX_MAX_REQ 64
@@ -139,14 +155,20 @@ int pdfx_eval_xfxQ(const pdfx_grid *g, const void *xf_dev, int prec,
 int pdfx_eval_alphas(const pdfx_grid *g, const double *q2, int64_t n, void *out,
                      int prec, int domain_mode, void *stream);
 
+/* Same with Q instead of Q^2 (Fig. 1 py_alphasQ): Q^2 = Q*Q is formed in FP64
+ * on the device, so the result is bit for bit that of pdfx_eval_alphas at the
+ * FP64 product Q*Q.  q device FP64 [n], GeV. */
+int pdfx_eval_alphasQ(const pdfx_grid *g, const double *q, int64_t n, void *out,
+                      int prec, int domain_mode, void *stream);
+
 /* x f and alpha_s at the same points in one call, as an integrand needs both
- * (Sec. 4's examples): the results of pdfx_eval_xfx(g, xf_dev, prec, pids,
+ * (Sec. 3.1; the examples of Sec. 3.2 and 3.3): the results of pdfx_eval_xfx(g, xf_dev, prec, pids,
  * n_req, x, q2, n_pts, out, domain_mode, stream) and of pdfx_eval_alphas(g,
  * q2, n_pts, as_out, prec, domain_mode, stream): x f bit for bit, alpha_s to
  * rounding (a few ulp), the same NaNs and the same domain counting (a point
  * with Q^2 outside counts once for each).  as_out:
- * device [n_pts], FP64 or FP32 per prec.  domain_mode PDFX_DOMAIN_NAN or
- * PDFX_DOMAIN_CLAMP.  When the alpha_s knots are the grid's Q^2 knots (same
+ * device [n_pts], FP64 or FP32 per prec.  domain_mode PDFX_DOMAIN_NAN,
+ * PDFX_DOMAIN_CLAMP or PDFX_DOMAIN_ERROR.  When the alpha_s knots are the grid's Q^2 knots (same
  * values, same subgrids), alpha_s is formed in the x f pass from the point's
  * Q^2 weights, one pass over the points instead of two; otherwise the two
  * passes run one after the other.  PDFX_ENOALPHAS if the grid has no alpha_s
@@ -292,6 +314,21 @@ int pdfx_set_lumi_launch(pdfx_grid *g, int prec, int32_t block, int32_t ppt);
 /* Number of out-of-grid points counted since the last call, over all eval
  * calls on g; synchronises the device, then resets the counter. */
 int pdfx_domain_errors(const pdfx_grid *g, int64_t *count);
+
+/* The same for the evaluations of a set (pdfx_eval_set_xfx counts a point
+ * once per member whose grid it is outside). */
+int pdfx_set_domain_errors(const pdfx_set *s, int64_t *count);
+
+/* Host-side domain check with the rule of the eval calls (Sec. 2.1 queries
+ * live inside the grid): counts the points of host arrays x[n], q2[n] (FP64,
+ * Q^2 in GeV^2) outside [x_0, x_last] x [q2_0, q2_last] of the grid that d
+ * describes, NaN included, into *n_outside (may be NULL).  Returns
+ * PDFX_EDOMAIN if there is one, PDFX_OK if there is none, PDFX_EINVAL for an
+ * invalid descriptor (the pdfx_load_grid rules; values may be absent) or
+ * NULL arrays with n > 0.  Touches no device: callers use it to vet inputs
+ * before uploading them. */
+int pdfx_check_points(const pdfx_grid_desc *d, const double *x, const double *q2, int64_t n,
+                      int64_t *n_outside);
 
 /* Measurement helper, not part of the method: the device's rate of aligned
  * 16-byte LDS reads, the ceiling of the stencil kernels (their stencils are

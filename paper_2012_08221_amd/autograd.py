@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import binding as B
-from .api import _DOMAIN, _device_f64, _stream, prec_code, prec_dtype
+from .api import _DOMAIN, _stream, prec_code, prec_dtype
 
 
 class XfxFunction(torch.autograd.Function):
@@ -50,8 +50,5 @@ class XfxFunction(torch.autograd.Function):
 def xfx(pdf, values, pids, x, q2, prec="f32s", domain="nan"):
     """x f for pids at (x, Q^2) from grid values `values` [n_flav, n_x, n_q],
     differentiable in values, x and q2 (x and q2 FP64 device tensors)."""
-    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
-        x = _device_f64(x)
-    if not (isinstance(q2, torch.Tensor) and q2.is_cuda and q2.dtype == torch.float64):
-        q2 = _device_f64(q2, x.device)
-    return XfxFunction.apply(values, x.contiguous(), q2.contiguous(), pdf, pids, prec, domain)
+    x, q2 = pdf._points(x, q2)
+    return XfxFunction.apply(values, x, q2, pdf, pids, prec, domain)

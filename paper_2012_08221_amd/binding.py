@@ -18,6 +18,7 @@ PDFX_OK = 0
 PDFX_EINVAL = -1
 PDFX_ENOMEM = -2
 PDFX_EHIP = -3
+PDFX_EDOMAIN = -4
 PDFX_ENOALPHAS = -5
 PDFX_ENOVALUES = -6
 PDFX_F64 = 0
@@ -25,6 +26,7 @@ PDFX_F32S = 1
 PDFX_DOMAIN_NAN = 0
 PDFX_DOMAIN_CLAMP = 1
 PDFX_DOMAIN_EXTRAPOLATE = 2
+PDFX_DOMAIN_ERROR = 3
 PDFX_MAX_REQ = 64
 
 # Launch shapes (workgroup size, points per thread) compiled into the forward
@@ -40,12 +42,12 @@ LAUNCH_SHAPES_F32 = ((512, 4),)
 # Every function the header declares, in header order.
 EXPORTS = (
     "pdfx_load_grid", "pdfx_free_grid", "pdfx_grid_shape", "pdfx_eval_xfx", "pdfx_eval_xfxQ",
-    "pdfx_eval_alphas", "pdfx_eval_xfx_alphas", "pdfx_eval_xfx_backward", "pdfx_load_set", "pdfx_free_set",
+    "pdfx_eval_alphas", "pdfx_eval_alphasQ", "pdfx_eval_xfx_alphas", "pdfx_eval_xfx_backward", "pdfx_load_set", "pdfx_free_set",
     "pdfx_eval_set_xfx", "pdfx_eval_dy", "pdfx_dy_max_blocks", "pdfx_eval_dy_backward",
     "pdfx_autotune", "pdfx_autotune_set", "pdfx_get_launch", "pdfx_set_launch",
     "pdfx_get_dy_launch", "pdfx_set_dy_launch",
     "pdfx_eval_lumi", "pdfx_get_lumi_launch", "pdfx_set_lumi_launch",
-    "pdfx_domain_errors", "pdfx_bench_lds", "pdfx_last_error", "pdfx_version",
+    "pdfx_domain_errors", "pdfx_set_domain_errors", "pdfx_check_points", "pdfx_bench_lds", "pdfx_last_error", "pdfx_version",
 )
 
 
@@ -53,6 +55,11 @@ class PdfxError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("pdfx error %d: %s" % (code, msg))
         self.code = code
+
+
+class PdfxDomainError(PdfxError):
+    """PDFX_EDOMAIN: a PDFX_DOMAIN_ERROR call found points outside the grid
+    (its outputs were written, NaN at those points)."""
 
 
 class GridDesc(ctypes.Structure):
@@ -91,6 +98,7 @@ def lib():
             "pdfx_eval_xfx": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, i32, vp], i32),
             "pdfx_eval_xfxQ": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, i32, vp], i32),
             "pdfx_eval_alphas": ([vp, vp, i64, vp, i32, i32, vp], i32),
+            "pdfx_eval_alphasQ": ([vp, vp, i64, vp, i32, i32, vp], i32),
             "pdfx_eval_xfx_alphas": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, vp, i32, vp], i32),
             "pdfx_eval_xfx_backward": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, vp, vp, vp, i32,
                                         vp], i32),
@@ -111,6 +119,8 @@ def lib():
             "pdfx_get_lumi_launch": ([vp, i32, vp, vp], i32),
             "pdfx_set_lumi_launch": ([vp, i32, i32, i32], i32),
             "pdfx_domain_errors": ([vp, vp], i32),
+            "pdfx_set_domain_errors": ([vp, vp], i32),
+            "pdfx_check_points": ([vp, vp, vp, i64, vp], i32),
             "pdfx_bench_lds": ([i32, i32, i32, vp, vp], i32),
             "pdfx_last_error": ([], ctypes.c_char_p),
             "pdfx_version": ([], ctypes.c_char_p),
@@ -125,7 +135,8 @@ def lib():
 
 def check(rc: int):
     if rc != PDFX_OK:
-        raise PdfxError(rc, lib().pdfx_last_error().decode())
+        cls = PdfxDomainError if rc == PDFX_EDOMAIN else PdfxError
+        raise cls(rc, lib().pdfx_last_error().decode())
     return rc
 
 
@@ -195,6 +206,10 @@ def pdfx_eval_xfx_alphas(h, xf_dev, prec, pids, x_ptr, q2_ptr, n_pts, out_ptr, a
 
 def pdfx_eval_alphas(h, q2_ptr, n, out_ptr, prec, domain_mode, stream):
     return check(lib().pdfx_eval_alphas(h, q2_ptr, n, out_ptr, prec, domain_mode, stream))
+
+
+def pdfx_eval_alphasQ(h, q_ptr, n, out_ptr, prec, domain_mode, stream):
+    return check(lib().pdfx_eval_alphasQ(h, q_ptr, n, out_ptr, prec, domain_mode, stream))
 
 
 def pdfx_eval_xfx_backward(h, xf_dev, prec, pids, x_ptr, q2_ptr, n_pts, gout_ptr, gxf_ptr,
@@ -296,6 +311,27 @@ def pdfx_set_lumi_launch(h, prec, block, ppt):
 def pdfx_domain_errors(h) -> int:
     c = ctypes.c_int64()
     check(lib().pdfx_domain_errors(h, ctypes.byref(c)))
+    return c.value
+
+
+def pdfx_set_domain_errors(h) -> int:
+    c = ctypes.c_int64()
+    check(lib().pdfx_set_domain_errors(h, ctypes.byref(c)))
+    return c.value
+
+
+def pdfx_check_points(desc: HostDesc, x, q2) -> int:
+    """Host arrays x, q2 against the grid that desc describes: the number of
+    points outside it (PDFX_EDOMAIN is not raised; invalid arguments are)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    q2 = np.ascontiguousarray(q2, dtype=np.float64)
+    if x.shape != q2.shape:
+        raise ValueError("x and q2 differ in length")
+    c = ctypes.c_int64()
+    rc = lib().pdfx_check_points(ctypes.byref(desc.desc), x.ctypes.data, q2.ctypes.data,
+                                 x.shape[0], ctypes.byref(c))
+    if rc not in (PDFX_OK, PDFX_EDOMAIN):
+        check(rc)
     return c.value
 
 

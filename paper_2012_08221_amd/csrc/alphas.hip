@@ -35,6 +35,8 @@ __global__ __launch_bounds__(kAsBlock) void alphas_kernel(const AlphasArgs a, Ax
             const int64_t p = t0 + (int64_t)j * kAsBlock + threadIdx.x;
             const bool live = p < a.n;
             double qv = qs[j];
+            if (a.q_is_q)
+                qv = qv * qv;
             const bool nan_in = qv != qv;
             bool ok = true;
             if (!(qv >= a.a.lo && qv <= a.a.hi)) {

@@ -216,10 +216,11 @@ struct DyArgs {
 struct AlphasArgs {
     AxisDev a;
     const void *vals;             // padded [n+2] FP64 or FP32: vals[k+1] = alpha_s knot k
-    const double *q2;
+    const double *q2;             // Q^2, or Q when q_is_q (squared in FP64 first)
     void *out;
     int64_t n;
     int domain_mode;
+    int q_is_q;
     unsigned long long *dom_count;
 };
 

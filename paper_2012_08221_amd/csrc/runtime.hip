@@ -42,6 +42,31 @@ int fail_hip(hipError_t e, const char *what)
 
 void clear_error() { g_last_error.clear(); }
 
+namespace {
+__global__ void zero_counter(unsigned long long *c) { *c = 0ull; }
+}  // namespace
+
+int error_mode_begin(void *counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, (unsigned long long *)counter);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PDFX_OK : fail_hip(e, "counter reset launch");
+}
+
+int error_mode_end(void *counter, hipStream_t s, int64_t *total)
+{
+    unsigned long long v = 0;
+    hipError_t e = hipMemcpyAsync(&v, counter, sizeof v, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail_hip(e, "read the call's domain count");
+    *total += (int64_t)v;
+    if (v)
+        return fail(PDFX_EDOMAIN, "%llu point(s) outside the grid", v);
+    return PDFX_OK;
+}
+
 DeviceBuf::~DeviceBuf()
 {
     if (ptr)
@@ -318,15 +343,24 @@ static int eval_xfx_common(const pdfx_grid *g, const void *xf_dev, int prec, con
     // EXTRAPOLATE: the forward pass in clamp mode, then the continuation
     // rewrites the rows of the points outside the grid
     const bool extrap = domain_mode == PDFX_DOMAIN_EXTRAPOLATE;
+    const bool err = domain_mode == PDFX_DOMAIN_ERROR;
     XfxArgs a;
     int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q, n_pts, out,
-                              extrap ? PDFX_DOMAIN_CLAMP : domain_mode, &a);
+                              extrap ? PDFX_DOMAIN_CLAMP : err ? PDFX_DOMAIN_NAN : domain_mode,
+                              &a);
     if (rc != PDFX_OK || n_pts == 0)
         return rc;
     if (extrap && ((uintptr_t)out & (prec == PDFX_F64 ? 7 : 3)))
         return fail(PDFX_EINVAL, "misaligned device pointer");
     a.q_is_q = q_is_q;
+    if (err) {
+        a.dom_count = (unsigned long long *)g->call_count.ptr;
+        if ((rc = error_mode_begin(g->call_count.ptr, (hipStream_t)stream)) != PDFX_OK)
+            return rc;
+    }
     rc = run_xfx(g, a, xf_dev, prec, (hipStream_t)stream);
+    if (rc == PDFX_OK && err)
+        return error_mode_end(g->call_count.ptr, (hipStream_t)stream, &g->host_count);
     if (rc != PDFX_OK || !extrap)
         return rc;
     ExtrapArgs e{};
@@ -391,6 +425,26 @@ int pdfx_eval_xfxQ(const pdfx_grid *g, const void *xf_dev, int prec, const int32
     return eval_xfx_common(g, xf_dev, prec, pids, n_req, x, q, n_pts, out, domain_mode, stream, 1);
 }
 
+// alpha_s launch after the argument checks; domain_mode NAN or CLAMP, outside
+// points counted in *counter.
+static int run_alphas(const pdfx_grid *g, const double *q, int64_t n, void *out, int prec,
+                      int domain_mode, hipStream_t stream, int q_is_q, void *counter)
+{
+    AlphasArgs a;
+    a.a = g->aa.dev();
+    a.vals = prec == PDFX_F64 ? g->as_vals64.ptr : g->as_vals32.ptr;
+    a.q2 = q;
+    a.out = out;
+    a.n = n;
+    a.domain_mode = domain_mode;
+    a.q_is_q = q_is_q;
+    a.dom_count = (unsigned long long *)counter;
+    hipError_t e = launch_alphas(a, prec == PDFX_F32S, stream);
+    if (e != hipSuccess)
+        return fail_hip(e, "alpha_s launch");
+    return PDFX_OK;
+}
+
 int pdfx_eval_xfx_alphas(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
                          int32_t n_req, const double *x, const double *q2, int64_t n_pts,
                          void *out, void *as_out, int domain_mode, void *stream)
@@ -400,29 +454,41 @@ int pdfx_eval_xfx_alphas(const pdfx_grid *g, const void *xf_dev, int prec, const
         return fail(PDFX_EINVAL, "grid is NULL");
     if (!g->has_alphas)
         return fail(PDFX_ENOALPHAS, "grid has no alpha_s knots");
-    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP)
-        return fail(PDFX_EINVAL, "domain mode %d: alpha_s takes NAN or CLAMP", domain_mode);
+    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP &&
+        domain_mode != PDFX_DOMAIN_ERROR)
+        return fail(PDFX_EINVAL, "domain mode %d: alpha_s takes NAN, CLAMP or ERROR",
+                    domain_mode);
+    const bool err = domain_mode == PDFX_DOMAIN_ERROR;
+    const int mode = err ? PDFX_DOMAIN_NAN : domain_mode;
     XfxArgs a;
-    int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q2, n_pts, out, domain_mode, &a);
+    int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q2, n_pts, out, mode, &a);
     if (rc != PDFX_OK || n_pts == 0)
         return rc;
     if (!as_out)
         return fail(PDFX_EINVAL, "as_out is NULL");
     if ((uintptr_t)as_out & (prec == PDFX_F64 ? 7 : 3))
         return fail(PDFX_EINVAL, "misaligned device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (err) {
+        a.dom_count = (unsigned long long *)g->call_count.ptr;
+        if ((rc = error_mode_begin(g->call_count.ptr, st)) != PDFX_OK)
+            return rc;
+    }
     bool as_done = false;
     if (g->alphas_on_q) {
         a.as_vals = prec == PDFX_F64 ? g->as_vals64.ptr : g->as_vals32.ptr;   // padded
         a.as_out = as_out;
     }
-    rc = run_xfx(g, a, xf_dev, prec, (hipStream_t)stream, &as_done);
-    if (rc != PDFX_OK || as_done)
-        return rc;
-    return pdfx_eval_alphas(g, q2, n_pts, as_out, prec, domain_mode, stream);
+    rc = run_xfx(g, a, xf_dev, prec, st, &as_done);
+    if (rc == PDFX_OK && !as_done)
+        rc = run_alphas(g, q2, n_pts, as_out, prec, mode, st, 0, a.dom_count);
+    if (rc == PDFX_OK && err)
+        return error_mode_end(g->call_count.ptr, st, &g->host_count);
+    return rc;
 }
 
-int pdfx_eval_alphas(const pdfx_grid *g, const double *q2, int64_t n, void *out, int prec,
-                     int domain_mode, void *stream)
+static int eval_alphas_common(const pdfx_grid *g, const double *q, int64_t n, void *out,
+                              int prec, int domain_mode, void *stream, int q_is_q)
 {
     clear_error();
     if (!g)
@@ -431,26 +497,38 @@ int pdfx_eval_alphas(const pdfx_grid *g, const double *q2, int64_t n, void *out,
         return fail(PDFX_ENOALPHAS, "grid has no alpha_s knots");
     if (prec != PDFX_F64 && prec != PDFX_F32S)
         return fail(PDFX_EINVAL, "unknown precision %d", prec);
-    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP)
+    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP &&
+        domain_mode != PDFX_DOMAIN_ERROR)
         return fail(PDFX_EINVAL, "unknown domain mode %d", domain_mode);
     if (n < 0)
         return fail(PDFX_EINVAL, "n < 0");
     if (n == 0)
         return PDFX_OK;
-    if (!q2 || !out)
+    if (!q || !out)
         return fail(PDFX_EINVAL, "q2 or out is NULL");
-    AlphasArgs a;
-    a.a = g->aa.dev();
-    a.vals = prec == PDFX_F64 ? g->as_vals64.ptr : g->as_vals32.ptr;
-    a.q2 = q2;
-    a.out = out;
-    a.n = n;
-    a.domain_mode = domain_mode;
-    a.dom_count = (unsigned long long *)g->dom_count.ptr;
-    hipError_t e = launch_alphas(a, prec == PDFX_F32S, (hipStream_t)stream);
-    if (e != hipSuccess)
-        return fail_hip(e, "alpha_s launch");
-    return PDFX_OK;
+    if (((uintptr_t)q & 7) || ((uintptr_t)out & (prec == PDFX_F64 ? 7 : 3)))
+        return fail(PDFX_EINVAL, "misaligned device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (domain_mode != PDFX_DOMAIN_ERROR)
+        return run_alphas(g, q, n, out, prec, domain_mode, st, q_is_q, g->dom_count.ptr);
+    int rc = error_mode_begin(g->call_count.ptr, st);
+    if (rc == PDFX_OK)
+        rc = run_alphas(g, q, n, out, prec, PDFX_DOMAIN_NAN, st, q_is_q, g->call_count.ptr);
+    if (rc == PDFX_OK)
+        rc = error_mode_end(g->call_count.ptr, st, &g->host_count);
+    return rc;
+}
+
+int pdfx_eval_alphas(const pdfx_grid *g, const double *q2, int64_t n, void *out, int prec,
+                     int domain_mode, void *stream)
+{
+    return eval_alphas_common(g, q2, n, out, prec, domain_mode, stream, 0);
+}
+
+int pdfx_eval_alphasQ(const pdfx_grid *g, const double *q, int64_t n, void *out, int prec,
+                      int domain_mode, void *stream)
+{
+    return eval_alphas_common(g, q, n, out, prec, domain_mode, stream, 1);
 }
 
 int pdfx_domain_errors(const pdfx_grid *g, int64_t *count)
@@ -468,7 +546,54 @@ int pdfx_domain_errors(const pdfx_grid *g, int64_t *count)
     e = hipMemset(g->dom_count.ptr, 0, sizeof v);
     if (e != hipSuccess)
         return fail_hip(e, "reset domain counter");
-    *count = (int64_t)v;
+    *count = (int64_t)v + g->host_count;
+    g->host_count = 0;
+    return PDFX_OK;
+}
+
+int pdfx_set_domain_errors(const pdfx_set *s, int64_t *count)
+{
+    clear_error();
+    if (!s || !count)
+        return fail(PDFX_EINVAL, "set or count is NULL");
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return fail_hip(e, "synchronize");
+    unsigned long long v = 0;
+    e = hipMemcpy(&v, s->dom_count.ptr, sizeof v, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return fail_hip(e, "read domain counter");
+    e = hipMemset(s->dom_count.ptr, 0, sizeof v);
+    if (e != hipSuccess)
+        return fail_hip(e, "reset domain counter");
+    *count = (int64_t)v + s->host_count;
+    s->host_count = 0;
+    return PDFX_OK;
+}
+
+int pdfx_check_points(const pdfx_grid_desc *d, const double *x, const double *q2, int64_t n,
+                      int64_t *n_outside)
+{
+    clear_error();
+    if (n_outside)
+        *n_outside = 0;
+    int rc = validate_desc(d, false);
+    if (rc != PDFX_OK)
+        return rc;
+    if (n < 0)
+        return fail(PDFX_EINVAL, "n < 0");
+    if (n > 0 && (!x || !q2))
+        return fail(PDFX_EINVAL, "x or q2 is NULL");
+    const double xlo = d->x[0], xhi = d->x[d->n_x - 1];
+    const double qlo = d->q2[0], qhi = d->q2[d->q_off[d->n_sub] - 1];
+    int64_t bad = 0;
+    for (int64_t p = 0; p < n; ++p)
+        bad += !(x[p] >= xlo && x[p] <= xhi && q2[p] >= qlo && q2[p] <= qhi);   // NaN: outside
+    if (n_outside)
+        *n_outside = bad;
+    if (bad)
+        return fail(PDFX_EDOMAIN, "%lld of %lld points outside the grid", (long long)bad,
+                    (long long)n);
     return PDFX_OK;
 }
 
@@ -732,7 +857,8 @@ int grid_init(pdfx_grid *g, const pdfx_grid_desc *d)
                          std::memcmp(aa.rec32.data(), aq.rec32.data(),
                                      aa.rec32.size() * sizeof(aa.rec32[0])) == 0;
     }
-    if ((e = g->dom_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess)
+    if ((e = g->dom_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess ||
+        (e = g->call_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess)
         return fail_hip(e, "allocate domain counter");
     g->shape[PDFX_F64] = default_shape(false);
     g->shape[PDFX_F32S] = default_shape(true);
@@ -1280,7 +1406,8 @@ int pdfx_load_set(const pdfx_grid_desc *members, int32_t n_mem, pdfx_set **out)
     hipError_t e;
     if ((e = s->mem_desc.upload(md.data(), md.size() * sizeof(MemberDev))) != hipSuccess ||
         (e = s->counter.upload(nullptr, 256)) != hipSuccess ||
-        (e = s->dom_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess) {
+        (e = s->dom_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess ||
+        (e = s->call_count.upload(nullptr, sizeof(unsigned long long))) != hipSuccess) {
         delete s;
         return fail_hip(e, "upload set descriptors");
     }
@@ -1302,6 +1429,9 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
     // argument checks and the column plan, as for one member
     XfxArgs fa;
     const pdfx_grid *g0 = s->members[0];
+    const bool err = domain_mode == PDFX_DOMAIN_ERROR;
+    if (err)
+        domain_mode = PDFX_DOMAIN_NAN;
     int rc = prepare_xfx_args(g0, nullptr, prec == PDFX_F64 ? PDFX_F32S : prec, pids, n_req, x,
                               q2, n_pts, out, domain_mode, &fa);
     if (rc != PDFX_OK)
@@ -1328,7 +1458,7 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
     a.n = n_pts;
     a.out = out;
     a.domain_mode = domain_mode;
-    a.dom_count = (unsigned long long *)s->dom_count.ptr;
+    a.dom_count = (unsigned long long *)(err ? s->call_count.ptr : s->dom_count.ptr);
     a.counter = (unsigned int *)s->counter.ptr;
     const LaunchShape ls = s->shape[prec];
     const int64_t tile_pts = (int64_t)ls.block * ls.ppt;
@@ -1400,6 +1530,12 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
                     dma ? "" : " (members beyond one slab need the double-buffered classes: "
                                "16-byte aligned output blocks and a set launch shape they "
                                "are compiled for)");
+    if (err && (rc = error_mode_begin(s->call_count.ptr, (hipStream_t)stream)) != PDFX_OK)
+        return rc;
+    auto done = [&]() {
+        return err ? error_mode_end(s->call_count.ptr, (hipStream_t)stream, &s->host_count)
+                   : PDFX_OK;
+    };
     if (dma) {
         for (int c = 0; c < kSetClasses; ++c) {
             if (s->cls_ids[prec][c].empty())
@@ -1409,7 +1545,7 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
                 return fail_hip(e, "set launch");
         }
         if (s->rest_ids[prec].empty())
-            return PDFX_OK;
+            return done();
         a.mem_ids = (const int *)s->ids_dev[prec][kSetClasses].ptr;
         a.n_items = (int)(s->rest_ids[prec].size() * ipm);
     }
@@ -1423,7 +1559,7 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
     e = launch_set(a, f32, ls_set, lds, s->cus, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail_hip(e, "set launch");
-    return PDFX_OK;
+    return done();
 }
 
 }  // extern "C"
@@ -1631,8 +1767,12 @@ int pdfx_eval_lumi(const pdfx_grid *g, const void *xf_dev, int prec, int32_t n_p
         return fail(PDFX_EINVAL, "n_pair = %d outside [1, %d]", n_pair, kLumiMaxPairs);
     if (!pid_a || !pid_b)
         return fail(PDFX_EINVAL, "pid_a or pid_b is NULL");
-    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP)
+    if (domain_mode != PDFX_DOMAIN_NAN && domain_mode != PDFX_DOMAIN_CLAMP &&
+        domain_mode != PDFX_DOMAIN_ERROR)
         return fail(PDFX_EINVAL, "unknown domain mode %d", domain_mode);
+    const bool err = domain_mode == PDFX_DOMAIN_ERROR;
+    if (err)
+        domain_mode = PDFX_DOMAIN_NAN;
     if (n < 0)
         return fail(PDFX_EINVAL, "n < 0");
     if (n > 0 && !out_pair && !out_sum)
@@ -1711,7 +1851,7 @@ int pdfx_eval_lumi(const pdfx_grid *g, const void *xf_dev, int prec, int32_t n_p
     a.out_pair = out_pair;
     a.out_sum = out_sum;
     a.domain_mode = domain_mode;
-    a.dom_count = (unsigned long long *)g->dom_count.ptr;
+    a.dom_count = (unsigned long long *)(err ? g->call_count.ptr : g->dom_count.ptr);
     LaunchShape ls = g->lumi_shape[prec];
     if (!g->lumi_pinned[prec] && ls.ppt > 1) {
         // a small call: (512, 1) gives twice or more the workgroups
@@ -1719,8 +1859,15 @@ int pdfx_eval_lumi(const pdfx_grid *g, const void *xf_dev, int prec, int32_t n_p
         if ((n + tile - 1) / tile < g->cus / 2)
             ls = LaunchShape{512, 1};
     }
+    if (err) {
+        const int rc = error_mode_begin(g->call_count.ptr, (hipStream_t)stream);
+        if (rc != PDFX_OK)
+            return rc;
+    }
     if ((e = launch_lumi(a, f32, ls, g->cus, (hipStream_t)stream)) != hipSuccess)
         return fail_hip(e, "luminosity launch");
+    if (err)
+        return error_mode_end(g->call_count.ptr, (hipStream_t)stream, &g->host_count);
     return PDFX_OK;
 }
 

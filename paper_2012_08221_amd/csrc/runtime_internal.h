@@ -73,6 +73,10 @@ struct pdfx_grid {
     pdfx::DeviceBuf scratch_gvals[2];        // caller values as flavour-group node slabs
     pdfx::DeviceBuf as_vals64, as_vals32;    // padded [n_as + 2]
     pdfx::DeviceBuf dom_count;               // unsigned long long
+    // PDFX_DOMAIN_ERROR calls: their own counter (cleared per call) and the
+    // total of the points they found, added to the pdfx_domain_errors count
+    pdfx::DeviceBuf call_count;              // unsigned long long
+    mutable int64_t host_count = 0;
     pdfx::LaunchShape shape[2];              // per precision
     // shape[prec] set by pdfx_set_launch: used as it is at every size (a tuned
     // or default shape gives way to (512, 1) when a call has too few points
@@ -108,6 +112,13 @@ int prepare_xfx_args(const pdfx_grid *g, const void *xf_dev, int prec, const int
 int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStream_t s,
             bool *as_done = nullptr);
 
+// Domain mode PDFX_DOMAIN_ERROR: the evaluation runs in NAN mode with its
+// outside points counted in a per-call counter that error_mode_begin clears
+// by a kernel on the stream; error_mode_end waits for the stream, adds the
+// count to *total and returns PDFX_EDOMAIN if it is not 0.
+int error_mode_begin(void *counter, hipStream_t s);
+int error_mode_end(void *counter, hipStream_t s, int64_t *total);
+
 }  // namespace pdfx
 
 struct pdfx_set {
@@ -116,6 +127,8 @@ struct pdfx_set {
     pdfx::DeviceBuf mem_desc;                // MemberDev[n_mem]
     pdfx::DeviceBuf counter;                 // work-list cursor
     pdfx::DeviceBuf dom_count;
+    pdfx::DeviceBuf call_count;              // PDFX_DOMAIN_ERROR calls, as for a grid
+    mutable int64_t host_count = 0;
     pdfx::LaunchShape shape[2] = {{512, 2}, {512, 2}};
     int tiles_per_item[2] = {4, 4};
     int cus = 256;

@@ -249,3 +249,37 @@ def dy_uniforms(chunk: int, n: int):
 
 # DY pids: quark q at x1 paired with antiquark -q at x2, q = 1..5.
 DY_QUARKS = np.array([1, 2, 3, 4, 5], dtype=np.int32)
+
+
+def threshold_jump_grid(n_x: int, n_sub: int, n_q_total: int, k: int = 30,
+                        jump: float = 0.25) -> GridSpec:
+    """A member whose two copies of each boundary Q^2 knot hold different values,
+    as when a parton switches on at its threshold: the generated values with the
+    upper copy of every boundary row raised by jump * (1 + |value|), and the
+    upper copy of every repeated alpha_s knot raised by 5%.  Thresholds as for
+    many-member grids (MEMBER_EDGES[n_sub])."""
+    params = draw_params(_streams(k)["params"])
+    g = make_grid(params, n_x, MEMBER_EDGES[n_sub], n_q_total)
+    for s in range(1, g.n_sub):
+        kk = int(g.q_off[s])
+        g.xf[:, :, kk] += jump * (1.0 + np.abs(g.xf[:, :, kk]))
+        g.as_val[kk] *= 1.05
+    return g
+
+
+def threshold_points(g: GridSpec, k: int, n_random: int, n_x_per_threshold: int):
+    """Query points for the threshold tie rule: n_random points log-uniform over
+    the grid, then for every threshold Q^2 (exactly, one ulp below and one ulp
+    above) the x knots and n_x_per_threshold log-uniform x.  Returns (x, q2)."""
+    rng = _streams(k)["queries"]
+    lx0, lx1 = math.log(g.x[0]), math.log(g.x[-1])
+    lq0, lq1 = math.log(g.q2[0]), math.log(g.q2[-1])
+    xs = [np.exp(lx0 + (lx1 - lx0) * rng.random(n_random))]
+    qs = [np.exp(lq0 + (lq1 - lq0) * rng.random(n_random))]
+    for s in range(1, g.n_sub):
+        thr = g.q2[g.q_off[s]]
+        xt = np.r_[g.x, np.exp(lx0 + (lx1 - lx0) * rng.random(n_x_per_threshold))]
+        for qv in (thr, np.nextafter(thr, 0.0), np.nextafter(thr, np.inf)):
+            xs.append(xt)
+            qs.append(np.full(xt.shape, qv))
+    return np.concatenate(xs), np.concatenate(qs)

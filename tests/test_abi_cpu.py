@@ -114,3 +114,65 @@ def test_member_grids_uneven():
     for m in ms:
         assert 50 <= m.n_x <= 200 and 20 <= m.n_q <= 80 and 2 <= m.n_sub <= 4
         assert np.all(np.diff(m.q_off) >= 4)
+
+
+def test_host_domain_check_returns_edomain(L):
+    """pdfx_check_points applies the eval calls' domain rule to host arrays:
+    PDFX_EDOMAIN with the count of outside points (NaN included), PDFX_OK
+    when every point is inside, PDFX_EINVAL for a bad descriptor."""
+    g = wl.config0_grid()
+    d = _desc(xf=None)
+    x, q2 = wl.queries(0, 1000)
+    n_out = ctypes.c_int64(-1)
+    xp, qp = x.ctypes.data, q2.ctypes.data
+    assert L.pdfx_check_points(ctypes.byref(d.desc), xp, qp, 1000, ctypes.byref(n_out)) == B.PDFX_OK
+    assert n_out.value == 0
+    # the grid's own edges are inside (closed interval)
+    ex = np.array([g.x[0], g.x[-1], g.x[0], g.x[-1]])
+    eq = np.array([g.q2[0], g.q2[-1], g.q2[-1], g.q2[0]])
+    assert B.pdfx_check_points(d, ex, eq) == 0
+    bad_x = x.copy()
+    bad_q = q2.copy()
+    bad_x[[3, 70]] = [np.nextafter(g.x[0], 0.0), 1.5]
+    bad_q[[5, 900]] = [np.nextafter(g.q2[0], 0.0), np.nan]
+    bad_x[11] = np.nan
+    rc = L.pdfx_check_points(ctypes.byref(d.desc), bad_x.ctypes.data, bad_q.ctypes.data, 1000,
+                             ctypes.byref(n_out))
+    assert rc == B.PDFX_EDOMAIN and n_out.value == 5
+    assert "outside" in B.last_error()
+    assert B.pdfx_check_points(d, bad_x, bad_q) == 5
+    assert L.pdfx_check_points(ctypes.byref(d.desc), None, None, 0, None) == B.PDFX_OK
+    assert L.pdfx_check_points(ctypes.byref(d.desc), None, None, 5, None) == B.PDFX_EINVAL
+    bad_desc = _desc(x=np.r_[g.x[:10], g.x[9:10], g.x[11:]])
+    assert L.pdfx_check_points(ctypes.byref(bad_desc.desc), xp, qp, 1000, None) == B.PDFX_EINVAL
+    assert L.pdfx_check_points(None, xp, qp, 1000, None) == B.PDFX_EINVAL
+
+
+def test_new_entry_points_reject_null_handles(L):
+    assert L.pdfx_eval_alphasQ(None, None, 10, None, 0, 0, None) == B.PDFX_EINVAL
+    assert L.pdfx_set_domain_errors(None, None) == B.PDFX_EINVAL
+
+
+def test_api_argument_checks_on_host_tensors():
+    """The torch API's checks (length, shape, dtype, device, contiguity) run
+    before any launch; here on CPU tensors against a CPU 'device'."""
+    import torch
+    from paper_2012_08221_amd import api
+    cpu = torch.device("cpu")
+    a = torch.zeros(5, dtype=torch.float64)
+    assert api._same_length(("x", a), ("q2", torch.zeros(5))) == 5
+    with pytest.raises(ValueError):
+        api._same_length(("x", a), ("q2", torch.zeros(4)))
+    api._check_tensor(torch.zeros(5, 3), (5, 3), torch.float32, cpu, "out")
+    with pytest.raises(ValueError):
+        api._check_tensor(torch.zeros(5, 2), (5, 3), torch.float32, cpu, "out")
+    with pytest.raises(TypeError):
+        api._check_tensor(torch.zeros(5, 3, dtype=torch.float64), (5, 3), torch.float32, cpu,
+                          "out")
+    with pytest.raises(ValueError):
+        api._check_tensor(torch.zeros(3, 5).t(), (5, 3), torch.float32, cpu, "out")
+    with pytest.raises(TypeError):
+        api._check_tensor(np.zeros((5, 3), np.float32), (5, 3), torch.float32, cpu, "out")
+    with pytest.raises(ValueError):
+        api._domain("wrap")
+    assert api._domain("error") == B.PDFX_DOMAIN_ERROR
