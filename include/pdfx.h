@@ -202,6 +202,26 @@ int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
                            double *grad_x, double *grad_q2,
                            int domain_mode, void *stream);
 
+/* Bytes of device scratch that pdfx_eval_xfx_backward_noalloc works in. */
+#define PDFX_NOALLOC_SCRATCH_BYTES (48u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same adjoint
+ * as pdfx_eval_xfx_backward, same arguments and results, but its workspace is
+ * a fixed device array of PDFX_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends, so the call allocates nothing.  It needs
+ * 256-byte-rounded n_pts * (4 + 1 + 4 * 8) bytes plus 8 * n_flav * n_x * n_q
+ * (about 1.3e6 points on an 11 x 100 x 50 grid); a larger call returns
+ * PDFX_EINVAL before enqueuing anything.  All calls on one GPU share that
+ * array: calls that may overlap on one GPU (other streams or host threads)
+ * race, so order them on one stream. */
+int pdfx_eval_xfx_backward_noalloc(const pdfx_grid *g, const void *xf_dev, int prec,
+                                   const int32_t *pids, int32_t n_req,
+                                   const double *x, const double *q2, int64_t n_pts,
+                                   const void *grad_out, void *grad_xf,
+                                   double *grad_x, double *grad_q2,
+                                   int domain_mode, void *stream);
+
 /* ---- many members in one launch (PDF sets are collections of members, Sec. 1) ---- */
 
 /* Loads n_mem members (each desc must carry values; grids may differ). */

@@ -42,7 +42,8 @@ LAUNCH_SHAPES_F32 = ((512, 4),)
 # Every function the header declares, in header order.
 EXPORTS = (
     "pdfx_load_grid", "pdfx_free_grid", "pdfx_grid_shape", "pdfx_eval_xfx", "pdfx_eval_xfxQ",
-    "pdfx_eval_alphas", "pdfx_eval_alphasQ", "pdfx_eval_xfx_alphas", "pdfx_eval_xfx_backward", "pdfx_load_set", "pdfx_free_set",
+    "pdfx_eval_alphas", "pdfx_eval_alphasQ", "pdfx_eval_xfx_alphas", "pdfx_eval_xfx_backward",
+    "pdfx_eval_xfx_backward_noalloc", "pdfx_load_set", "pdfx_free_set",
     "pdfx_eval_set_xfx", "pdfx_eval_dy", "pdfx_dy_max_blocks", "pdfx_eval_dy_backward",
     "pdfx_autotune", "pdfx_autotune_set", "pdfx_get_launch", "pdfx_set_launch",
     "pdfx_get_dy_launch", "pdfx_set_dy_launch",
@@ -102,6 +103,8 @@ def lib():
             "pdfx_eval_xfx_alphas": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, vp, i32, vp], i32),
             "pdfx_eval_xfx_backward": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, vp, vp, vp, i32,
                                         vp], i32),
+            "pdfx_eval_xfx_backward_noalloc": ([vp, vp, i32, vp, i32, vp, vp, i64, vp, vp, vp, vp,
+                                                i32, vp], i32),
             "pdfx_load_set": ([vp, i32, vp], i32),
             "pdfx_free_set": ([vp], None),
             "pdfx_eval_set_xfx": ([vp, i32, vp, i32, vp, vp, i64, vp, i32, vp], i32),
@@ -218,6 +221,17 @@ def pdfx_eval_xfx_backward(h, xf_dev, prec, pids, x_ptr, q2_ptr, n_pts, gout_ptr
     return check(lib().pdfx_eval_xfx_backward(h, xf_dev, prec, p, arr.shape[0], x_ptr, q2_ptr,
                                               n_pts, gout_ptr, gxf_ptr, gx_ptr, gq2_ptr,
                                               domain_mode, stream))
+
+
+def pdfx_eval_xfx_backward_noalloc(h, xf_dev, prec, pids, x_ptr, q2_ptr, n_pts, gout_ptr,
+                                   gxf_ptr, gx_ptr, gq2_ptr, domain_mode, stream):
+    arr, p = _pids(pids)
+    return check(lib().pdfx_eval_xfx_backward_noalloc(h, xf_dev, prec, p, arr.shape[0], x_ptr,
+                                                      q2_ptr, n_pts, gout_ptr, gxf_ptr, gx_ptr,
+                                                      gq2_ptr, domain_mode, stream))
+
+
+PDFX_NOALLOC_SCRATCH_BYTES = 48 * 1024 * 1024
 
 
 def pdfx_load_set(descs) -> int:

@@ -1094,14 +1094,16 @@ int pdfx_grid::max_blocks(int prec, const pdfx::XfxArgs &a, int kernel,
 // adjoint
 // ---------------------------------------------------------------------------
 
-extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
-                                      const int32_t *pids, int32_t n_req, const double *x,
-                                      const double *q2, int64_t n_pts, const void *grad_out,
-                                      void *grad_xf, double *grad_x, double *grad_q2,
-                                      int domain_mode, void *stream)
+namespace pdfx {
+
+// The adjoint with its workspace either grown in the grid (fixed_ws NULL) or
+// taken from fixed_ws, fixed_cap bytes, which a call that needs more rejects
+// before enqueuing anything.
+int eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
+                      int32_t n_req, const double *x, const double *q2, int64_t n_pts,
+                      const void *grad_out, void *grad_xf, double *grad_x, double *grad_q2,
+                      int domain_mode, void *stream, void *fixed_ws, size_t fixed_cap)
 {
-    using namespace pdfx;
-    clear_error();
     XfxArgs fa;
     // grad_out takes the place of `out` in the argument checks
     int rc = prepare_xfx_args(g, xf_dev, prec, pids, n_req, x, q2, n_pts,
@@ -1127,12 +1129,6 @@ extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, in
                     dma_supported(LaunchShape{512, 1}, fa.nx, fa.nq, fa.ax.nbuckets,
                                   fa.aq.nbuckets);
     }
-    if (xf_dev && want_coord && !coord_fwd) {
-        RepackArgs r{xf_dev, g->scratch_vals[prec].ptr, g->nf, fa.nx, fa.nq, fa.slab_elems};
-        if ((e = launch_repack(r, prec == PDFX_F32S, s)) != hipSuccess)
-            return fail_hip(e, "repack launch");
-        fa.vals = g->scratch_vals[prec].ptr;
-    }
     // workspace: idx, flag, tx, tq, accx, accw per point + the FP64 knot accumulator
     const int64_t n = n_pts;
     const size_t nv = (size_t)g->nf * fa.nx * fa.nq;
@@ -1140,11 +1136,27 @@ extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, in
     const size_t o_idx = 0, o_flag = o_idx + al(4 * n), o_tx = o_flag + al(n),
                  o_tq = o_tx + al(8 * n), o_ax = o_tq + al(8 * n), o_aw = o_ax + al(8 * n),
                  o_g = o_aw + al(8 * n), total = o_g + al(8 * nv);
-    if (g->bwd_ws.bytes < total) {
-        if ((e = g->bwd_ws.upload(nullptr, total)) != hipSuccess)
-            return fail_hip(e, "allocate adjoint workspace");
+    char *ws;
+    if (fixed_ws) {
+        if (total > fixed_cap)
+            return fail(PDFX_EINVAL,
+                        "%lld points on a %zu-value grid need %zu bytes of adjoint workspace; "
+                        "the allocation-free call has %zu",
+                        (long long)n, nv, total, fixed_cap);
+        ws = (char *)fixed_ws;
+    } else {
+        if (g->bwd_ws.bytes < total) {
+            if ((e = g->bwd_ws.upload(nullptr, total)) != hipSuccess)
+                return fail_hip(e, "allocate adjoint workspace");
+        }
+        ws = (char *)g->bwd_ws.ptr;
     }
-    char *ws = (char *)g->bwd_ws.ptr;
+    if (xf_dev && want_coord && !coord_fwd) {
+        RepackArgs r{xf_dev, g->scratch_vals[prec].ptr, g->nf, fa.nx, fa.nq, fa.slab_elems};
+        if ((e = launch_repack(r, prec == PDFX_F32S, s)) != hipSuccess)
+            return fail_hip(e, "repack launch");
+        fa.vals = g->scratch_vals[prec].ptr;
+    }
     BwdArgs a{};
     a.ax = fa.ax;
     a.aq = fa.aq;
@@ -1193,6 +1205,19 @@ extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, in
     if (e != hipSuccess)
         return fail_hip(e, "adjoint launch");
     return PDFX_OK;
+}
+
+}  // namespace pdfx
+
+extern "C" int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
+                                      const int32_t *pids, int32_t n_req, const double *x,
+                                      const double *q2, int64_t n_pts, const void *grad_out,
+                                      void *grad_xf, double *grad_x, double *grad_q2,
+                                      int domain_mode, void *stream)
+{
+    pdfx::clear_error();
+    return pdfx::eval_xfx_backward(g, xf_dev, prec, pids, n_req, x, q2, n_pts, grad_out, grad_xf,
+                                   grad_x, grad_q2, domain_mode, stream, nullptr, 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -119,6 +119,14 @@ int run_xfx(const pdfx_grid *g, XfxArgs &a, const void *xf_dev, int prec, hipStr
 int error_mode_begin(void *counter, hipStream_t s);
 int error_mode_end(void *counter, hipStream_t s, int64_t *total);
 
+// The adjoint (pdfx_eval_xfx_backward) with its workspace grown in the grid
+// (fixed_ws NULL) or taken from fixed_ws of fixed_cap bytes; a call that
+// needs more than fixed_cap is rejected before anything is enqueued.
+int eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec, const int32_t *pids,
+                      int32_t n_req, const double *x, const double *q2, int64_t n_pts,
+                      const void *grad_out, void *grad_xf, double *grad_x, double *grad_q2,
+                      int domain_mode, void *stream, void *fixed_ws, size_t fixed_cap);
+
 }  // namespace pdfx
 
 struct pdfx_set {
