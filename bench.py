@@ -33,6 +33,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VEC_TFLOPS = 78.6         # MI355X vector FP64
+FP32_VEC_TFLOPS = 157.3        # MI355X vector FP32 (no packed math)
 N_PTS = 10_000_000
 METRIC = "PDF evals/sec (points×flavours) FP32 vs FP64 at stated rel. error; fwd+bwd/s"
 
@@ -140,18 +142,32 @@ def main():
     stream = torch.cuda.current_stream()
 
     def timed(fn, reps, warm=1):
-        """Mean ms per call over `reps` calls, HIP events on the launch stream."""
+        """Median ms per call over `reps` calls (at least 20 for calls under
+        10 ms), each bracketed by HIP events on the launch stream."""
         for _ in range(warm):
             fn()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
+        ev = []
+        for i in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             fn()
-        e1.record(stream)
+            e1.record(stream)
+            ev.append((e0, e1))
+            if i == 0 and reps < 20:
+                torch.cuda.synchronize()
+                if e0.elapsed_time(e1) < 10.0:
+                    reps = 20
+        while len(ev) < reps:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            ev.append((e0, e1))
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
     def copy_gbs():
         """HBM bandwidth a plain copy reaches: 1 GiB of FP64 read, 1 GiB written."""
@@ -189,6 +205,60 @@ def main():
                                                      stream.cuda_stream), 5)
             rates[name] = blocks * 256 * iters / (ms * 1e-3)
         return rates
+
+    lds_cache = {}
+    atomic_cache = {}
+
+    def atomics_all():
+        if not atomic_cache:
+            atomic_cache.update(lds_atomic_rates())
+        return atomic_cache
+
+    def lds_meas_all():
+        if not lds_cache:
+            lds_cache.update(lds_read_gbs())
+        return lds_cache
+
+    def dy_fractions(prec, npts, chunk, ms_f, ms_b, lds, atomics, nx, nq, shape):
+        """LDS and VALU fractions of the integrand (bound by neither HBM nor
+        MFMA).  Forward LDS: the method's 164 values per point (10 partons x 16
+        knots + 4 alpha_s) and the kernel's own node reads and slab copies, both
+        against the measured LDS read rates.  VALU: the stencil arithmetic (2
+        flops per multiply-add: 16 + 4 per parton, 4 for alpha_s) in the value
+        precision plus the per-point FP64 work (3 weight folds of ~30 flops, 2 exp
+        and 1 log at ~40 flops each, luminosity and Jacobian ~12), against
+        MI355X's vector peaks.  Backward: 10 partons x 16 knot adds per point
+        against the measured 64-bit LDS atomic rate."""
+        vb = 8 if prec == "f64" else 4
+        g = 16 // vb
+        stencils = 6 if prec == "f64" else 4          # FP32: the middle group at both sides
+        slabs = 12 // g
+        tile = shape[0] * shape[1]
+        tiles = npts // chunk * ((chunk + tile - 1) // tile)
+        alg = npts * 164 * vb
+        kern = npts * stencils * 16 * 16 + tiles * slabs * nx * nq * 16
+        t = ms_f * 1e-3
+        f_val = 10 * 2 * 20 + 2 * 4                  # flops in the value precision
+        f_64 = 3 * 30 + 3 * 40 + 12                    # FP64 flops per point
+        if prec == "f64":
+            f_64 += f_val
+            t_peak = npts * f_64 / (FP64_VEC_TFLOPS * 1e12)
+        else:
+            t_peak = npts * (f_64 / (FP64_VEC_TFLOPS * 1e12) + f_val / (FP32_VEC_TFLOPS * 1e12))
+        adds = npts * 10 * 16
+        return {
+            "forward_lds": {"algorithmic_bytes_per_point": 164 * vb,
+                            "algorithmic_gbs": alg / t / 1e9,
+                            "kernel_bytes": kern, "kernel_gbs": kern / t / 1e9,
+                            "frac_of_stream": kern / t / 1e9 / lds["measured_stream_gbs"],
+                            "frac_of_random": kern / t / 1e9 / lds["measured_random_gbs"]},
+            "forward_valu": {"flops_per_point_fp64": f_64,
+                             "flops_per_point_fp32": 0 if prec == "f64" else f_val,
+                             "time_at_vector_peak_ms": t_peak * 1e3,
+                             "frac": t_peak / t},
+            "backward_lds_atomics": {"adds": adds, "adds_per_s": adds / (ms_b * 1e-3),
+                                     "frac_of_u64_random": adds / (ms_b * 1e-3)
+                                     / atomics["u64_random_per_s"]}}
 
     if args.calib_copy:
         n, ms, gbs = copy_gbs()
@@ -242,9 +312,10 @@ def main():
             t1.record(stream)
             torch.cuda.synchronize()
             ms = t0.elapsed_time(t1) / args.steps
-            k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-            results[prec] = {"ms": ms, "xfx_ms": k_ms, "out": out, "as": aout,
-                             "launch": list(pdf.launch(prec))}
+            per = [a.elapsed_time(b) for a, b in ev]
+            k_ms = float(np.mean(per))
+            results[prec] = {"ms": ms, "xfx_ms": k_ms, "median_ms": float(np.median(per)),
+                             "out": out, "as": aout, "launch": list(pdf.launch(prec))}
             log("%s: %.3f ms per step, xfx kernel %.3f ms" % (prec, ms, k_ms))
         if args.only == "xfx":
             r = results[args.prec]
@@ -308,7 +379,7 @@ def main():
             "n_points": nb, "dtype": "f32 stencil forward, FP64 adjoint",
             "what": "sum w*xf, gradients w.r.t. the 11x100x50 knots, x and Q^2",
             "knot_scatter_atomics": nb * nf * 16,
-            "lds_atomic_64bit": lds_atomic_rates()}
+            "lds_atomic_64bit": atomics_all()}
         log("fwd+bwd: %.3f ms (forward %.3f)" % (ms_fb, ms_f))
         if args.only == "bwd":
             print(json.dumps({"only": "bwd", **variants["fwd_bwd"]}))
@@ -329,8 +400,9 @@ def main():
             outm = torch.empty((101, nm, nf), dtype=api.prec_dtype(prec), device=dev)
             ms = timed(lambda: pset.xfxQ2(pids, xm, qm, prec=prec, out=outm), 3 if args.only else 5)
             bpe = 8 if prec == "f64" else 4
+            gbs = (101 * nm * nf * bpe + 16 * nm) / ms / 1e6
             mres[prec] = {"value": 101 * nm * nf / (ms * 1e-3), "unit": "pf/s", "ms": ms,
-                          "hbm_gbs_algorithmic": (101 * nm * nf * bpe + 16 * nm) / ms / 1e6}
+                          "hbm_gbs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
             del outm
             log("members %s: %.3f ms" % (prec, ms))
         variants["members"] = {"n_members": 101, "n_points": nm, **mres}
@@ -415,7 +487,9 @@ def main():
             ms_f = timed(fwd_all, 2)
             ms_b = timed(bwd_all, 2)
             npts = nchunk * csize
-            dres[prec] = {"forward_points_per_s": npts / (ms_f * 1e-3),
+            fr = dy_fractions(prec, npts, csize, ms_f, ms_b, lds_meas_all(), atomics_all(),
+                              grid.n_x, grid.n_q, best)
+            dres[prec] = {**fr, "forward_points_per_s": npts / (ms_f * 1e-3),
                           "backward_points_per_s": npts / (ms_b * 1e-3),
                           "forward_ms_per_chunk": ms_f / nchunk,
                           "backward_ms_per_chunk": ms_b / nchunk,
@@ -465,8 +539,10 @@ def main():
             vb = 8 if prec == "f64" else 4
             lres[prec] = {"sum_ms": ms_s, "sum_points_per_s": nl / (ms_s * 1e-3),
                           "sum_hbm_gbs_algorithmic": nl * (16 + vb) / ms_s / 1e6,
+                          "sum_hbm_frac": nl * (16 + vb) / ms_s / 1e6 / HBM_PEAK_GBS,
                           "pairs_and_sum_ms": ms_b,
                           "pairs_and_sum_hbm_gbs_algorithmic": nl * (16 + 5 * vb) / ms_b / 1e6,
+                          "pairs_and_sum_hbm_frac": nl * (16 + 5 * vb) / ms_b / 1e6 / HBM_PEAK_GBS,
                           "launch_shape": list(best),
                           "shape_sum_ms": {"%dx%d" % k: v for k, v in tune.items()}}
             log("lumi %s: sum %.3f ms, pairs+sum %.3f ms" % (prec, ms_s, ms_b))
@@ -538,7 +614,7 @@ def main():
                          "per_flavour_max": [float(v) for v in e.max(axis=0)],
                          "points_checked": ns}
 
-    lds_meas = lds_read_gbs() if results else {}
+    lds_meas = lds_meas_all() if results else {}
     for prec, r in results.items():
         bpp = 16 + (nf + 1) * (8 if prec == "f64" else 4)
         variants[prec] = {

@@ -228,10 +228,16 @@ int pdfx_eval_xfx_backward_noalloc(const pdfx_grid *g, const void *xf_dev, int p
 int pdfx_load_set(const pdfx_grid_desc *members, int32_t n_mem, pdfx_set **out);
 void pdfx_free_set(pdfx_set *s);
 
-/* out[m][p][r] = x f^{(m)}_{pids[r]}(x[p], q2[p]) for every member m, in one
- * persistent launch that walks a (point tile, member) work list.  x, q2 device
- * FP64 [n_pts] shared by all members; out device [n_mem][n_pts][n_req] FP64
- * or FP32 by precision. */
+/* out[m][p][r] = x f^{(m)}_{pids[r]}(x[p], q2[p]) for every member m.  x, q2
+ * device FP64 [n_pts] shared by all members; out device [n_mem][n_pts][n_req]
+ * FP64 or FP32 by precision.  Every member evaluates in one persistent launch
+ * (after a one-thread kernel that resets its work-list cursor) that walks a
+ * single list of (member, run of point tiles) items, the members of the
+ * dearest node-width classes first; each item runs its member's class.  A
+ * member too large for every class (beyond about 19k knots in FP64) is
+ * evaluated by a second, single-slab launch, and so is every member when
+ * `out` or the member blocks are not 16-byte aligned or the request touches
+ * more flavour groups than a class holds results for. */
 int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t n_req,
                       const double *x, const double *q2, int64_t n_pts,
                       void *out, int domain_mode, void *stream);

@@ -1322,12 +1322,28 @@ static int set_build_classes(pdfx_set *s, const pdfx_grid_desc *members, int n_m
     if ((e = s->dma_mem.upload(md.data(), md.size() * sizeof(SetMemberDev))) != hipSuccess)
         return fail_hip(e, "upload set descriptors");
     for (int p = 0; p < 2; ++p) {
-        for (int c = 0; c <= kSetClasses; ++c) {
-            const std::vector<int> &ids = c < kSetClasses ? s->cls_ids[p][c] : s->rest_ids[p];
-            if (!ids.empty() &&
-                (e = s->ids_dev[p][c].upload(ids.data(), ids.size() * sizeof(int))) != hipSuccess)
-                return fail_hip(e, "upload set work lists");
+        // one work list for every class: dearest classes first, and inside a
+        // class the largest grids first
+        std::vector<int> order;
+        for (int o = 0; o < kSetClasses; ++o) {
+            const int c = kSetClassOrder[o];
+            std::vector<int> ids = s->cls_ids[p][c];
+            std::stable_sort(ids.begin(), ids.end(), [&](int u, int v) {
+                return md[u].nx * md[u].nq > md[v].nx * md[v].nq;
+            });
+            for (int m : ids) {
+                order.push_back(m);
+                order.push_back(c);
+            }
         }
+        s->n_order[p] = (int)order.size() / 2;
+        if (!order.empty() &&
+            (e = s->order_dev[p].upload(order.data(), order.size() * sizeof(int))) != hipSuccess)
+            return fail_hip(e, "upload set work list");
+        if (!s->rest_ids[p].empty() &&
+            (e = s->rest_dev[p].upload(s->rest_ids[p].data(),
+                                       s->rest_ids[p].size() * sizeof(int))) != hipSuccess)
+            return fail_hip(e, "upload set work list");
     }
     return PDFX_OK;
 }
@@ -1499,53 +1515,60 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
     a.n_items = (int)(a.n_mem * ipm);
     const bool f32 = prec == PDFX_F32S;
     hipError_t e;
-    // Double-buffered classes: a launch shape they are compiled for, 16-byte
-    // aligned member blocks, and a request whose groups fit every class's
-    // result slots.  The other members (or all, otherwise) go through the
-    // single-slab kernel.
-    SetDmaArgs d[kSetClasses];
+    // Double-buffered classes, all in one launch: a launch shape the kernel
+    // is compiled for, 16-byte aligned member blocks, and a request whose
+    // groups fit the result slots of every group width G its classes use.
+    // The other members (or all, otherwise) go through the single-slab kernel.
+    SetDmaArgs d{};
+    const int vs = f32 ? 4 : 8;
     bool dma = set_dma_shape_supported(ls, f32) && (uintptr_t)out % 16 == 0 &&
-               (n_pts * n_req * (f32 ? 4 : 8)) % 16 == 0;
+               (n_pts * n_req * vs) % 16 == 0 && s->n_order[prec] > 0;
+    bool have_dup = false;
     for (int c = 0; c < kSetClasses && dma; ++c) {
         if (s->cls_ids[prec][c].empty())
             continue;
+        const int G = kSetClassWidth[c] / vs;
+        const int gi = G == 1 ? 0 : G == 2 ? 1 : 2;
         XfxArgs plan = fa;
-        if (!plan_stages(plan, kSetClassWidth[c] / (f32 ? 4 : 8))) {
+        if (!plan_stages(plan, G)) {
             dma = false;
             break;
         }
-        SetDmaArgs &da = d[c];
-        da = SetDmaArgs{};
-        da.mem = (const SetMemberDev *)s->dma_mem.ptr;
-        da.ids = (const int *)s->ids_dev[prec][c].ptr;
-        da.n_ids = (int)s->cls_ids[prec][c].size();
-        da.items_per_member = (int)ipm;
-        da.tiles_per_item = (int)tpi;
-        da.n_items = (int)(da.n_ids * ipm);
-        da.counter = a.counter;
-        da.n_req = n_req;
-        da.n_stage = plan.n_stage;
-        da.n_zero = plan.n_zero;
-        da.n_dup = plan.n_dup;
+        d.plan[gi].n_stage = plan.n_stage;
         for (int k = 0; k < kGrpMaxSlots; ++k) {
-            da.sgrp[k] = plan.sgrp[k];
-            da.slot_col[k] = plan.slot_col[k];
+            d.plan[gi].sgrp[k] = plan.sgrp[k];
+            d.plan[gi].slot_col[k] = plan.slot_col[k];
         }
-        for (int k = 0; k < kMaxReq; ++k) {
-            da.zcols[k] = plan.zcols[k];
-            da.dup_src[k] = plan.dup_src[k];
-            da.dup_dst[k] = plan.dup_dst[k];
+        if (!have_dup) {   // the repeated columns do not depend on G
+            have_dup = true;
+            d.n_zero = plan.n_zero;
+            d.n_dup = plan.n_dup;
+            for (int k = 0; k < kMaxReq; ++k) {
+                d.zcols[k] = plan.zcols[k];
+                d.dup_src[k] = plan.dup_src[k];
+                d.dup_dst[k] = plan.dup_dst[k];
+            }
         }
-        da.x = x;
-        da.q = q2;
-        da.n = n_pts;
-        da.out = out;
-        da.domain_mode = domain_mode;
-        da.dom_count = a.dom_count;
-        int64_t pass = (int64_t)kSetSlabBytes / ((int64_t)n_req * (f32 ? 4 : 8)) / 16 * 16;
+    }
+    if (dma) {
+        d.mem = (const SetMemberDev *)s->dma_mem.ptr;
+        d.ids = (const int2 *)s->order_dev[prec].ptr;
+        d.n_ids = s->n_order[prec];
+        d.items_per_member = (int)ipm;
+        d.tiles_per_item = (int)tpi;
+        d.n_items = (int)(d.n_ids * ipm);
+        d.counter = a.counter;
+        d.n_req = n_req;
+        d.x = x;
+        d.q = q2;
+        d.n = n_pts;
+        d.out = out;
+        d.domain_mode = domain_mode;
+        d.dom_count = a.dom_count;
+        int64_t pass = (int64_t)kSetSlabBytes / ((int64_t)n_req * vs) / 16 * 16;
         if (pass > tile_pts)
             pass = tile_pts;
-        da.out_pass_pts = (int)pass;
+        d.out_pass_pts = (int)pass;
     }
     // the single-slab kernel takes the members outside the classes (all of
     // them without the classes) and needs each one's slab in LDS
@@ -1562,16 +1585,11 @@ int pdfx_eval_set_xfx(const pdfx_set *s, int prec, const int32_t *pids, int32_t 
                    : PDFX_OK;
     };
     if (dma) {
-        for (int c = 0; c < kSetClasses; ++c) {
-            if (s->cls_ids[prec][c].empty())
-                continue;
-            if ((e = launch_set_dma(d[c], f32, kSetClassWidth[c], kSetClassSplit[c], ls, s->cus,
-                                    (hipStream_t)stream)) != hipSuccess)
-                return fail_hip(e, "set launch");
-        }
+        if ((e = launch_set_dma(d, f32, ls, s->cus, (hipStream_t)stream)) != hipSuccess)
+            return fail_hip(e, "set launch");
         if (s->rest_ids[prec].empty())
             return done();
-        a.mem_ids = (const int *)s->ids_dev[prec][kSetClasses].ptr;
+        a.mem_ids = (const int *)s->rest_dev[prec].ptr;
         a.n_items = (int)(s->rest_ids[prec].size() * ipm);
     }
     // the single-slab kernel runs the FP32-only class shape as (512, 2): tiles

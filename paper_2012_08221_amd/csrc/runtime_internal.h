@@ -144,8 +144,10 @@ struct pdfx_set {
     pdfx::DeviceBuf dma_mem;                 // SetMemberDev[n_mem]
     std::vector<pdfx::DeviceBuf *> dma_vals; // group slabs of every member and precision
     int max_nx = 0, max_nq = 0;              // largest member grid (tuning key)
-    std::vector<int> cls_ids[2][pdfx::kSetClasses];   // members per class (node width 16, 8, 4, split 8)
+    std::vector<int> cls_ids[2][pdfx::kSetClasses];   // members per class (kSetClassWidth, kSetClassSplit)
     std::vector<int> rest_ids[2];            // members left to the single-slab kernel
-    pdfx::DeviceBuf ids_dev[2][pdfx::kSetClasses + 1];   // the lists above on the device
+    pdfx::DeviceBuf order_dev[2];            // the classes' work list: (member, class) pairs
+    int n_order[2] = {0, 0};
+    pdfx::DeviceBuf rest_dev[2];             // rest_ids on the device
     ~pdfx_set();
 };

@@ -3,10 +3,11 @@
 //
 // Each member's grid is stored as borderless flavour-group node slabs whose
 // node width NB (16, 8 or 4 bytes: G = NB / sizeof(value) flavours per node)
-// is the widest for which two slabs of the member fit the static LDS.  The
-// members of one node width form a class; each class is one persistent launch
-// over a work list of (member, run of point tiles) items taken from an atomic
-// cursor.  Per item the workgroup loads the member's knots and bucket seeds
+// is the widest for which two slabs of the member fit the static LDS; the
+// members of one node width (or split layout) form a class.  One persistent
+// launch walks a single work list of (member, run of point tiles) items,
+// dearest classes first, taken from an atomic cursor; each item runs its
+// class's body.  Per item the workgroup loads the member's knots and bucket seeds
 // into LDS; per tile it locates its points in the member's grid, walks the
 // request's flavour groups with the next group's slab copied into the spare
 // LDS slab by global-to-LDS loads (one barrier per stage), keeps the results
@@ -79,33 +80,245 @@ __device__ __forceinline__ void weights_g<float>(const AxisDev &ax, int i, doubl
     fwd::fold<float>(t, r[2], r[3], r[4], r[5], r[6], r[7], w);
 }
 
+// LDS of the set kernel, shared by every class body.
+struct SetLds {
+    uint4 *slab0, *slab1;
+    double *knots;
+    uint16_t *seeds;
+};
+
+// One work item of class (NB, SPLIT): a run of point tiles of member m.
 // SPLIT: the member's group slab (8- or 16-byte nodes) is too large for one
-// LDS slab; its rows [0, split_rows) go to slab0 and the rest to
-// slab1, so a stage holds one group in both slabs, copied while no stencil
-// runs.
-template <typename V, int NB, int BLOCK, int PPT, bool SPLIT>
-__global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
+// LDS slab; its rows [0, split_rows) go to slab0 and the rest to slab1, so a
+// stage holds one group in both slabs, copied while no stencil runs.
+// `loaded` is the member whose knots and seeds are in LDS (kept across items).
+template <typename V, int NB, bool SPLIT, int BLOCK, int PPT>
+__device__ __forceinline__ void set_item(const SetDmaArgs &a, const SetPlan &pl, const SetLds sh,
+                                         int m, int item, int mi, int &loaded, fwd::LAxis &lx,
+                                         fwd::LAxis &lq)
 {
     constexpr int G = NB / (int)sizeof(V);
     constexpr int NS = kGrpMaxSlots / G;
     constexpr int NSG = NS * G;
+    constexpr bool F32 = sizeof(V) == 4;
+    uint4 *const slab0 = sh.slab0;
+    uint4 *const slab1 = sh.slab1;
+    const int tid = threadIdx.x;
+    const int prec = F32 ? 1 : 0;
+    const int n_req = a.n_req;
+    const int n_stage = pl.n_stage;
+    const int64_t tile_pts = (int64_t)BLOCK * PPT;
+    const int64_t ntiles = (a.n + tile_pts - 1) / tile_pts;
+    const int64_t t_first = (int64_t)(item - mi * a.items_per_member) * a.tiles_per_item;
+    const int64_t t_end = t_first + a.tiles_per_item < ntiles ? t_first + a.tiles_per_item : ntiles;
+    const SetMemberDev &md = a.mem[m];
+    const int nx = md.nx, nq = md.nq;
+    const int chunks = (nx * nq * NB + 15) / 16;   // 16-byte chunks per slab
+    const uint4 *gsrc = reinterpret_cast<const uint4 *>(md.gvals[prec]);
+    const size_t gstride = (size_t)md.gstride[prec] * NB / 16;   // chunks per group
+    // split layout: rows below r_split in slab0, the others in slab1
+    const int r_split = SPLIT ? md.split_rows[prec] : nx;
+    const int chunks0 = SPLIT ? r_split * nq * NB / 16 : chunks;   // r_split * nq is even
+    const int chunks1 = SPLIT ? chunks - chunks0 : 0;
+    auto load_group = [&](int grp) {
+        const uint4 *src = gsrc + (size_t)grp * gstride;
+        fwd::dma_slab<BLOCK>(slab0, src, chunks0);
+        if (SPLIT)
+            fwd::dma_slab<BLOCK>(slab1, src + chunks0, chunks1);
+    };
+    if (n_stage > 0)
+        load_group(pl.sgrp[0]);
+    if (m != loaded) {
+        copy_words_g(reinterpret_cast<char *>(sh.knots), md.ax.knots, nx * 8, BLOCK);
+        copy_words_g(reinterpret_cast<char *>(sh.knots + nx), md.aq.knots, nq * 8, BLOCK);
+        copy_words_g(reinterpret_cast<char *>(sh.seeds), md.ax.seed, md.ax.nbuckets * 2, BLOCK);
+        copy_words_g(reinterpret_cast<char *>(sh.seeds + md.ax.nbuckets), md.aq.seed,
+                     md.aq.nbuckets * 2, BLOCK);
+        lx.k = sh.knots;
+        lx.seed = sh.seeds;
+        lx.n = nx;
+        lx.nb = md.ax.nbuckets;
+        lx.ln_lo = md.ax.ln_lo;
+        lx.inv_hb = md.ax.inv_hb;
+        lq.k = sh.knots + nx;
+        lq.seed = sh.seeds + md.ax.nbuckets;
+        lq.n = nq;
+        lq.nb = md.aq.nbuckets;
+        lq.ln_lo = md.aq.ln_lo;
+        lq.inv_hb = md.aq.inv_hb;
+        loaded = m;
+        __syncthreads();
+    }
+    V *out = reinterpret_cast<V *>(a.out) + (int64_t)m * a.n * n_req;
+
+    for (int64_t tile = t_first; tile < t_end; ++tile) {
+        const int64_t t0 = tile * tile_pts;
+        const bool more = tile + 1 < t_end;
+        if (SPLIT && tile > t_first && n_stage > 0) {
+            __syncthreads();   // the previous tile's output rows have left both slabs
+            load_group(pl.sgrp[0]);
+        }
+        V wx[PPT][4], wq[PPT][4];
+        int base[PPT], brow[PPT];
+        bool ok[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const int64_t p = t0 + tid + (int64_t)j * BLOCK;
+            double xv = load_point(a.x, p, a.n);
+            double qv = load_point(a.q, p, a.n);
+            const bool nan_in = (xv != xv) || (qv != qv);
+            const bool inside = xv >= md.ax.lo && xv <= md.ax.hi && qv >= md.aq.lo &&
+                                qv <= md.aq.hi;
+            ok[j] = true;
+            if (!inside) {
+                if (a.domain_mode == 1 && !nan_in) {
+                    xv = fmin(fmax(xv, md.ax.lo), md.ax.hi);
+                    qv = fmin(fmax(qv, md.aq.lo), md.aq.hi);
+                } else {
+                    ok[j] = false;
+                    xv = md.ax.lo;
+                    qv = md.aq.lo;
+                }
+            }
+            fwd::count_flagged(p < a.n && !ok[j], a.dom_count);
+            const double lnx = log(xv), lnq = log(qv);
+            const int ix = fwd::lbin(lx, xv, lnx);
+            const int kq = fwd::lbin(lq, qv, lnq);
+            weights_g<V>(md.ax, ix, lnx, wx[j]);
+            weights_g<V>(md.aq, kq, lnq, wq[j]);
+            brow[j] = fwd::window(ix, nx, wx[j]);
+            base[j] = fwd::window(kq, nq, wq[j]);   // column; the row is brow
+            if (!SPLIT)
+                base[j] += brow[j] * nq;
+        }
+
+        fwd::wait_vm();
+        __syncthreads();   // the tile's first group has landed
+
+        V res[PPT][NSG];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (s < n_stage) {
+                const bool last = s + 1 == n_stage;
+                const char *cur = reinterpret_cast<const char *>((s & 1) && !SPLIT ? slab1 : slab0);
+                if (SPLIT && s > 0) {
+                    __syncthreads();   // the previous group's stencils are done
+                    load_group(pl.sgrp[s]);
+                    fwd::wait_vm();
+                    __syncthreads();
+                }
+                if (!SPLIT && !last)
+                    fwd::dma_slab<BLOCK>((s & 1) ? slab0 : slab1,
+                                         gsrc + (size_t)pl.sgrp[s + 1] * gstride, chunks);
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    V acc[G];
+#pragma unroll
+                    for (int jx = 0; jx < 4; ++jx) {
+                        const char *rowp;
+                        if (SPLIT) {
+                            const int r = brow[j] + jx;
+                            const bool hi = r >= r_split;
+                            rowp = reinterpret_cast<const char *>(hi ? slab1 : slab0) +
+                                   (size_t)((hi ? r - r_split : r) * nq + base[j]) * NB;
+                        } else {
+                            rowp = cur + (size_t)(base[j] + jx * nq) * NB;
+                        }
+                        V r[G];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            V v[G];
+                            node_get<V, NB>(rowp + k * NB, v);
+#pragma unroll
+                            for (int g = 0; g < G; ++g)
+                                r[g] = (k == 0) ? wq[j][0] * v[g] : fma(wq[j][k], v[g], r[g]);
+                        }
+#pragma unroll
+                        for (int g = 0; g < G; ++g)
+                            acc[g] = (jx == 0) ? wx[j][0] * r[g] : fma(wx[j][jx], r[g], acc[g]);
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        res[j][s * G + g] = ok[j] ? acc[g] : fwd::quiet_nan<V>();
+                }
+                if (!SPLIT && !last) {
+                    fwd::wait_vm();
+                    __syncthreads();
+                }
+            }
+        }
+
+        // Output rows, assembled in both slabs (rows [0, cap) of a pass in
+        // slab1, the next cap in slab0; cap is a multiple of 16 rows) and
+        // written as 16-byte chunks, slab0's part first: on the last pass
+        // the next tile's first group then goes into slab0 while slab1's
+        // part is written.
+        __syncthreads();   // every stencil read is done
+        const int valid = (int)(a.n - t0 < tile_pts ? a.n - t0 : tile_pts);
+        const int cap = a.out_pass_pts;
+        const int rb = n_req * (int)sizeof(V);
+        auto write_rows = [&](const uint4 *src, char *dst, int bytes) {
+            const int nch = bytes >> 4;
+            for (int c = tid; c < nch; c += BLOCK)
+                *reinterpret_cast<uint4 *>(dst + c * 16) = src[c];
+            if (tid < (bytes & 15) / 4)
+                reinterpret_cast<uint32_t *>(dst + nch * 16)[tid] =
+                    reinterpret_cast<const uint32_t *>(src + nch)[tid];
+        };
+        for (int pa = 0; pa < valid; pa += 2 * cap) {
+            const int pn = valid - pa < 2 * cap ? valid - pa : 2 * cap;
+            if (pa > 0)
+                __syncthreads();   // the previous pass has left LDS
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const int lp = tid + j * BLOCK - pa;
+                if (lp >= 0 && lp < pn) {
+                    V *r = reinterpret_cast<V *>(lp < cap ? slab1 : slab0) +
+                           (lp < cap ? lp : lp - cap) * n_req;
+#pragma unroll
+                    for (int k = 0; k < NSG; ++k)
+                        if (k < n_stage * G && pl.slot_col[k] >= 0)
+                            r[pl.slot_col[k]] = res[j][k];
+                    for (int z = 0; z < a.n_zero; ++z)
+                        r[a.zcols[z]] = V(0);
+                    for (int d = 0; d < a.n_dup; ++d)
+                        r[a.dup_dst[d]] = r[a.dup_src[d]];
+                }
+            }
+            __syncthreads();
+            const int n1 = pn < cap ? pn : cap;   // rows in slab1; pn - n1 in slab0
+            char *dst = reinterpret_cast<char *>(out + (t0 + pa) * n_req);   // 16-byte aligned
+            if (pn > n1)
+                write_rows(slab0, dst + n1 * rb, (pn - n1) * rb);
+            // slab0 is re-filled when it held another group or output rows
+            if (!SPLIT && pa + 2 * cap >= valid && more &&
+                (n_stage > 1 || (n_stage == 1 && valid > cap))) {
+                if (pn > n1)
+                    __syncthreads();   // slab0's rows are read
+                fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)pl.sgrp[0] * gstride, chunks);
+            }
+            write_rows(slab1, dst, n1 * rb);
+        }
+    }
+}
+
+// The set kernel: one persistent launch over the work list of every class.
+// Each item names its member's class, and the workgroup runs that class's
+// body (node width NB, split or not); all bodies share the LDS arrays.
+template <typename V, int BLOCK, int PPT>
+__global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
+{
     constexpr bool F32 = sizeof(V) == 4;
     __shared__ uint4 slab0[kSetSlabBytes / 16];
     __shared__ uint4 slab1[kSetSlabBytes / 16];
     __shared__ double knots[kSetKnots];
     __shared__ uint16_t seeds[kSetSeeds];
     __shared__ int s_item;
-    const int tid = threadIdx.x;
-    const int prec = F32 ? 1 : 0;
-    const int n_req = a.n_req;
-    const int n_stage = a.n_stage;
-    const int64_t tile_pts = (int64_t)BLOCK * PPT;
-    const int64_t ntiles = (a.n + tile_pts - 1) / tile_pts;
+    const SetLds sh{slab0, slab1, knots, seeds};
     int loaded = -1;
     fwd::LAxis lx, lq;
-
     for (;;) {
-        if (tid == 0)
+        if (threadIdx.x == 0)
             s_item = (int)atomicAdd(a.counter, 1u);
         __syncthreads();
         const int item = s_item;
@@ -113,204 +326,36 @@ __global__ __launch_bounds__(BLOCK) void set_dma_kernel(const SetDmaArgs a)
         if (item >= a.n_items)
             break;
         const int mi = item / a.items_per_member;
-        const int m = a.ids[mi];
-        const int64_t t_first = (int64_t)(item - mi * a.items_per_member) * a.tiles_per_item;
-        const int64_t t_end = t_first + a.tiles_per_item < ntiles ? t_first + a.tiles_per_item : ntiles;
-        const SetMemberDev &md = a.mem[m];
-        const int nx = md.nx, nq = md.nq;
-        const int chunks = (nx * nq * NB + 15) / 16;   // 16-byte chunks per slab
-        const uint4 *gsrc = reinterpret_cast<const uint4 *>(md.gvals[prec]);
-        const size_t gstride = (size_t)md.gstride[prec] * NB / 16;   // chunks per group
-        // split layout: rows below r_split in slab0, the others in slab1
-        const int r_split = SPLIT ? md.split_rows[prec] : nx;
-        const int chunks0 = SPLIT ? r_split * nq * NB / 16 : chunks;   // r_split * nq is even
-        const int chunks1 = SPLIT ? chunks - chunks0 : 0;
-        auto load_group = [&](int grp) {
-            const uint4 *src = gsrc + (size_t)grp * gstride;
-            fwd::dma_slab<BLOCK>(slab0, src, chunks0);
-            if (SPLIT)
-                fwd::dma_slab<BLOCK>(slab1, src + chunks0, chunks1);
-        };
-        if (n_stage > 0)
-            load_group(a.sgrp[0]);
-        if (m != loaded) {
-            copy_words_g(reinterpret_cast<char *>(knots), md.ax.knots, nx * 8, BLOCK);
-            copy_words_g(reinterpret_cast<char *>(knots + nx), md.aq.knots, nq * 8, BLOCK);
-            copy_words_g(reinterpret_cast<char *>(seeds), md.ax.seed, md.ax.nbuckets * 2, BLOCK);
-            copy_words_g(reinterpret_cast<char *>(seeds + md.ax.nbuckets), md.aq.seed,
-                         md.aq.nbuckets * 2, BLOCK);
-            lx.k = knots;
-            lx.seed = seeds;
-            lx.n = nx;
-            lx.nb = md.ax.nbuckets;
-            lx.ln_lo = md.ax.ln_lo;
-            lx.inv_hb = md.ax.inv_hb;
-            lq.k = knots + nx;
-            lq.seed = seeds + md.ax.nbuckets;
-            lq.n = nq;
-            lq.nb = md.aq.nbuckets;
-            lq.ln_lo = md.aq.ln_lo;
-            lq.inv_hb = md.aq.inv_hb;
-            loaded = m;
-            __syncthreads();
-        }
-        V *out = reinterpret_cast<V *>(a.out) + (int64_t)m * a.n * n_req;
-
-        for (int64_t tile = t_first; tile < t_end; ++tile) {
-            const int64_t t0 = tile * tile_pts;
-            const bool more = tile + 1 < t_end;
-            if (SPLIT && tile > t_first && n_stage > 0) {
-                __syncthreads();   // the previous tile's output rows have left both slabs
-                load_group(a.sgrp[0]);
-            }
-            V wx[PPT][4], wq[PPT][4];
-            int base[PPT], brow[PPT];
-            bool ok[PPT];
-#pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                const int64_t p = t0 + tid + (int64_t)j * BLOCK;
-                double xv = load_point(a.x, p, a.n);
-                double qv = load_point(a.q, p, a.n);
-                const bool nan_in = (xv != xv) || (qv != qv);
-                const bool inside = xv >= md.ax.lo && xv <= md.ax.hi && qv >= md.aq.lo &&
-                                    qv <= md.aq.hi;
-                ok[j] = true;
-                if (!inside) {
-                    if (a.domain_mode == 1 && !nan_in) {
-                        xv = fmin(fmax(xv, md.ax.lo), md.ax.hi);
-                        qv = fmin(fmax(qv, md.aq.lo), md.aq.hi);
-                    } else {
-                        ok[j] = false;
-                        xv = md.ax.lo;
-                        qv = md.aq.lo;
-                    }
-                }
-                fwd::count_flagged(p < a.n && !ok[j], a.dom_count);
-                const double lnx = log(xv), lnq = log(qv);
-                const int ix = fwd::lbin(lx, xv, lnx);
-                const int kq = fwd::lbin(lq, qv, lnq);
-                weights_g<V>(md.ax, ix, lnx, wx[j]);
-                weights_g<V>(md.aq, kq, lnq, wq[j]);
-                brow[j] = fwd::window(ix, nx, wx[j]);
-                base[j] = fwd::window(kq, nq, wq[j]);   // column; the row is brow
-                if (!SPLIT)
-                    base[j] += brow[j] * nq;
-            }
-
-            fwd::wait_vm();
-            __syncthreads();   // the tile's first group has landed
-
-            V res[PPT][NSG];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (s < n_stage) {
-                    const bool last = s + 1 == n_stage;
-                    const char *cur = reinterpret_cast<const char *>((s & 1) && !SPLIT ? slab1 : slab0);
-                    if (SPLIT && s > 0) {
-                        __syncthreads();   // the previous group's stencils are done
-                        load_group(a.sgrp[s]);
-                        fwd::wait_vm();
-                        __syncthreads();
-                    }
-                    if (!SPLIT && !last)
-                        fwd::dma_slab<BLOCK>((s & 1) ? slab0 : slab1,
-                                             gsrc + (size_t)a.sgrp[s + 1] * gstride, chunks);
-#pragma unroll
-                    for (int j = 0; j < PPT; ++j) {
-                        V acc[G];
-#pragma unroll
-                        for (int jx = 0; jx < 4; ++jx) {
-                            const char *rowp;
-                            if (SPLIT) {
-                                const int r = brow[j] + jx;
-                                const bool hi = r >= r_split;
-                                rowp = reinterpret_cast<const char *>(hi ? slab1 : slab0) +
-                                       (size_t)((hi ? r - r_split : r) * nq + base[j]) * NB;
-                            } else {
-                                rowp = cur + (size_t)(base[j] + jx * nq) * NB;
-                            }
-                            V r[G];
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                V v[G];
-                                node_get<V, NB>(rowp + k * NB, v);
-#pragma unroll
-                                for (int g = 0; g < G; ++g)
-                                    r[g] = (k == 0) ? wq[j][0] * v[g] : fma(wq[j][k], v[g], r[g]);
-                            }
-#pragma unroll
-                            for (int g = 0; g < G; ++g)
-                                acc[g] = (jx == 0) ? wx[j][0] * r[g] : fma(wx[j][jx], r[g], acc[g]);
-                        }
-#pragma unroll
-                        for (int g = 0; g < G; ++g)
-                            res[j][s * G + g] = ok[j] ? acc[g] : fwd::quiet_nan<V>();
-                    }
-                    if (!SPLIT && !last) {
-                        fwd::wait_vm();
-                        __syncthreads();
-                    }
-                }
-            }
-
-            // Output rows, assembled in both slabs (rows [0, cap) of a pass in
-            // slab1, the next cap in slab0; cap is a multiple of 16 rows) and
-            // written as 16-byte chunks, slab0's part first: on the last pass
-            // the next tile's first group then goes into slab0 while slab1's
-            // part is written.
-            __syncthreads();   // every stencil read is done
-            const int valid = (int)(a.n - t0 < tile_pts ? a.n - t0 : tile_pts);
-            const int cap = a.out_pass_pts;
-            const int rb = n_req * (int)sizeof(V);
-            auto write_rows = [&](const uint4 *src, char *dst, int bytes) {
-                const int nch = bytes >> 4;
-                for (int c = tid; c < nch; c += BLOCK)
-                    *reinterpret_cast<uint4 *>(dst + c * 16) = src[c];
-                if (tid < (bytes & 15) / 4)
-                    reinterpret_cast<uint32_t *>(dst + nch * 16)[tid] =
-                        reinterpret_cast<const uint32_t *>(src + nch)[tid];
-            };
-            for (int pa = 0; pa < valid; pa += 2 * cap) {
-                const int pn = valid - pa < 2 * cap ? valid - pa : 2 * cap;
-                if (pa > 0)
-                    __syncthreads();   // the previous pass has left LDS
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    const int lp = tid + j * BLOCK - pa;
-                    if (lp >= 0 && lp < pn) {
-                        V *r = reinterpret_cast<V *>(lp < cap ? slab1 : slab0) +
-                               (lp < cap ? lp : lp - cap) * n_req;
-#pragma unroll
-                        for (int k = 0; k < NSG; ++k)
-                            if (k < n_stage * G && a.slot_col[k] >= 0)
-                                r[a.slot_col[k]] = res[j][k];
-                        for (int z = 0; z < a.n_zero; ++z)
-                            r[a.zcols[z]] = V(0);
-                        for (int d = 0; d < a.n_dup; ++d)
-                            r[a.dup_dst[d]] = r[a.dup_src[d]];
-                    }
-                }
-                __syncthreads();
-                const int n1 = pn < cap ? pn : cap;   // rows in slab1; pn - n1 in slab0
-                char *dst = reinterpret_cast<char *>(out + (t0 + pa) * n_req);   // 16-byte aligned
-                if (pn > n1)
-                    write_rows(slab0, dst + n1 * rb, (pn - n1) * rb);
-                // slab0 is re-filled when it held another group or output rows
-                if (!SPLIT && pa + 2 * cap >= valid && more &&
-                    (n_stage > 1 || (n_stage == 1 && valid > cap))) {
-                    if (pn > n1)
-                        __syncthreads();   // slab0's rows are read
-                    fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * gstride, chunks);
-                }
-                write_rows(slab1, dst, n1 * rb);
-            }
+        const int2 mc = a.ids[mi];
+        const int m = mc.x;
+        switch (mc.y) {
+        case 0:   // 16-byte nodes, G = 2 (FP64) or 4 (FP32)
+            set_item<V, 16, false, BLOCK, PPT>(a, a.plan[F32 ? 2 : 1], sh, m, item, mi, loaded,
+                                               lx, lq);
+            break;
+        case 1:   // 8-byte nodes, G = 1 or 2
+            set_item<V, 8, false, BLOCK, PPT>(a, a.plan[F32 ? 1 : 0], sh, m, item, mi, loaded,
+                                              lx, lq);
+            break;
+        case 2:   // 4-byte nodes (FP32 only), G = 1
+            if constexpr (F32)
+                set_item<V, 4, false, BLOCK, PPT>(a, a.plan[0], sh, m, item, mi, loaded, lx, lq);
+            break;
+        case 3:   // 8-byte nodes split over both slabs
+            set_item<V, 8, true, BLOCK, PPT>(a, a.plan[F32 ? 1 : 0], sh, m, item, mi, loaded,
+                                             lx, lq);
+            break;
+        default:  // 16-byte nodes split over both slabs
+            set_item<V, 16, true, BLOCK, PPT>(a, a.plan[F32 ? 2 : 1], sh, m, item, mi, loaded,
+                                              lx, lq);
+            break;
         }
     }
 }
 
 constexpr LaunchShape kSetDmaShapes[] = {{512, 1}, {512, 2}, {256, 2}};
 
-template <typename V, int NB, bool SPLIT = false>
+template <typename V>
 hipError_t launch_typed(const SetDmaArgs &a, LaunchShape ls, int cus, hipStream_t s)
 {
     auto go = [&](auto fn, int block) -> hipError_t {
@@ -324,14 +369,14 @@ hipError_t launch_typed(const SetDmaArgs &a, LaunchShape ls, int cus, hipStream_
         return hipGetLastError();
     };
     if (ls.block == 512 && ls.ppt == 1)
-        return go(set_dma_kernel<V, NB, 512, 1, SPLIT>, 512);
+        return go(set_dma_kernel<V, 512, 1>, 512);
     if (ls.block == 512 && ls.ppt == 2)
-        return go(set_dma_kernel<V, NB, 512, 2, SPLIT>, 512);
+        return go(set_dma_kernel<V, 512, 2>, 512);
     if (ls.block == 256 && ls.ppt == 2)
-        return go(set_dma_kernel<V, NB, 256, 2, SPLIT>, 256);
+        return go(set_dma_kernel<V, 256, 2>, 256);
     if constexpr (sizeof(V) == 4) {
         if (ls.block == 512 && ls.ppt == 4)
-            return go(set_dma_kernel<V, NB, 512, 4, SPLIT>, 512);
+            return go(set_dma_kernel<V, 512, 4>, 512);
     }
     return hipErrorInvalidValue;
 }
@@ -376,32 +421,9 @@ bool set_dma_shape_supported(LaunchShape ls, bool f32)
     return false;
 }
 
-hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, bool split, LaunchShape ls,
-                          int cus, hipStream_t s)
+hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, LaunchShape ls, int cus, hipStream_t s)
 {
-    if (split) {
-        if (nb == 8)
-            return f32 ? launch_typed<float, 8, true>(a, ls, cus, s)
-                       : launch_typed<double, 8, true>(a, ls, cus, s);
-        if (nb == 16)
-            return f32 ? launch_typed<float, 16, true>(a, ls, cus, s)
-                       : launch_typed<double, 16, true>(a, ls, cus, s);
-        return hipErrorInvalidValue;
-    }
-    if (f32) {
-        if (nb == 16)
-            return launch_typed<float, 16>(a, ls, cus, s);
-        if (nb == 8)
-            return launch_typed<float, 8>(a, ls, cus, s);
-        if (nb == 4)
-            return launch_typed<float, 4>(a, ls, cus, s);
-    } else {
-        if (nb == 16)
-            return launch_typed<double, 16>(a, ls, cus, s);
-        if (nb == 8)
-            return launch_typed<double, 8>(a, ls, cus, s);
-    }
-    return hipErrorInvalidValue;
+    return f32 ? launch_typed<float>(a, ls, cus, s) : launch_typed<double>(a, ls, cus, s);
 }
 
 }  // namespace pdfx

@@ -16,6 +16,10 @@ constexpr int kSetSeeds = 1280;
 constexpr int kSetClasses = 5;
 constexpr int kSetClassWidth[kSetClasses] = {16, 8, 4, 8, 16};
 constexpr bool kSetClassSplit[kSetClasses] = {false, false, false, true, true};
+// Order in which the classes enter the work list: dearest per tile first
+// (split 8-byte, split 16-byte, 8-byte, 16-byte, 4-byte), so that the cheap
+// items are left for the end of the launch and fill its tail.
+constexpr int kSetClassOrder[kSetClasses] = {3, 4, 1, 0, 2};
 
 // One member as the double-buffered set kernel sees it.
 struct SetMemberDev {
@@ -27,16 +31,25 @@ struct SetMemberDev {
     int split_rows[2];      // per precision, split classes: rows held in the first slab
 };
 
+// Stage plan of a request for one group width G (as XfxArgs): the groups
+// touched, in order, and the output column of each result slot.
+struct SetPlan {
+    int n_stage;
+    int sgrp[kGrpMaxSlots];
+    int slot_col[kGrpMaxSlots];
+};
+
+// The work list of one launch: every member that a class takes, in class
+// order (kSetClassOrder), each split into items_per_member runs of
+// tiles_per_item point tiles; workgroups take items from an atomic cursor.
 struct SetDmaArgs {
     const SetMemberDev *mem;   // [n_mem]
-    const int *ids;            // members of this launch's class
+    const int2 *ids;           // work order: (member, class)
     int n_ids;
     int items_per_member, tiles_per_item, n_items;
     unsigned int *counter;     // work-list cursor (reset before the launch)
-    // request plan for this class's group width (as XfxArgs)
-    int n_req, n_stage, n_zero, n_dup;
-    int sgrp[kGrpMaxSlots];
-    int slot_col[kGrpMaxSlots];
+    int n_req, n_zero, n_dup;
+    SetPlan plan[3];           // for G = 1, 2, 4
     int zcols[kMaxReq];
     int dup_src[kMaxReq], dup_dst[kMaxReq];
     const double *x, *q;       // shared points, q = Q^2
@@ -83,10 +96,8 @@ int set_node_bytes(int nx, int nq, int nbx, int nby, bool f32);
 // 0 if it does not fit that way.
 int set_split_rows(int nx, int nq, int nbx, int nbq, int nb);
 
-// Launches the class kernel of node width nb (split: an FP64 split class)
-// over args' work list.
-hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, int nb, bool split, LaunchShape ls,
-                          int cus, hipStream_t s);
+// Launches the set kernel over args' work list (one launch for every class).
+hipError_t launch_set_dma(const SetDmaArgs &a, bool f32, LaunchShape ls, int cus, hipStream_t s);
 // (512, 4) is compiled for FP32 only.
 bool set_dma_shape_supported(LaunchShape ls, bool f32);
 
