@@ -193,8 +193,9 @@ int pdfx_eval_xfx_alphas(const pdfx_grid *g, const void *xf_dev, int prec,
  * terms that uses max |grad_out| over the workgroup's points: resolution
  * about 2^-43 of that bound at 1e7 points), then added across workgroups
  * with FP64 device atomics, so results are reproducible up to the FP64 order
- * of those sums; there a non-finite grad_out value makes its flavour's whole
- * knot gradient NaN.  Larger grids sum with FP64 atomics. */
+ * of those sums.  Larger grids sum with FP64 atomics.  Either way a
+ * non-finite grad_out value reaches only the knots of its point's stencil
+ * (knots i-1 .. i+2 along each axis, cut at the axis ends). */
 int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
                            const int32_t *pids, int32_t n_req,
                            const double *x, const double *q2, int64_t n_pts,

@@ -191,8 +191,12 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
 // points out to lanes by the base's bank (wave_deal); only the point index
 // moves, and invalid points sort last and are skipped.  The sums are kept in
 // 64-bit fixed point (fixed_point.h): per flavour, a sweep over the chunk
-// finds max |dL/dout| and the scale follows from it and the axes' weight-sum
-// bounds.  Non-finite dL/dout makes that flavour's gradient NaN.
+// finds max |dL/dout| over its finite values and the scale follows from it
+// and the axes' weight-sum bounds.  A non-finite dL/dout skips the fixed-point
+// sums: its 16 products go to the FP64 accumulator by global atomics on the
+// knots of the point's stencil (the window of knots i-1 .. i+2 cut at the
+// axis ends), so it poisons those knots only, as the FP64-atomic adjoint
+// does.
 constexpr int kKnotGroup = 3;
 constexpr int kKnotBlock = 1024;
 
@@ -229,8 +233,11 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
             continue;
 #pragma unroll
         for (int j = 0; j < kKnotGroup; ++j)
-            if (j < nu)
-                m[j] = nan_max(m[j], fabs(gval(u0 + j, p)));
+            if (j < nu) {
+                const double ag = fabs(gval(u0 + j, p));
+                if (ag < 1.0 / 0.0)   // finite (false for NaN)
+                    m[j] = fmax(m[j], ag);
+            }
     }
     for (int i = threadIdx.x; i < nx - 1; i += kKnotBlock)
         m[kKnotGroup] = fmax(m[kKnotGroup], weight_sum_bound(a.ax.rec64[i]));
@@ -293,17 +300,38 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
         double wx[4], wq[4];
         fwd::fold<double>(a.st_tx[p], rx.pl, rx.plql, rx.ql, rx.qr, rx.qrpr, rx.pr, wx);
         fwd::fold<double>(a.st_tq[p], rq.pl, rq.plql, rq.ql, rq.qr, rq.qrpr, rq.pr, wq);
+        double wx0[4], wq0[4];   // weights of knots ix-1 .. ix+2, kq-1 .. kq+2
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            wx0[i] = wx[i];
+            wq0[i] = wq[i];
+        }
         const int base = fwd::window(ix, nx, wx) * nq + fwd::window(kq, nq, wq);
 #pragma unroll
         for (int j = 0; j < kKnotGroup; ++j) {
             if (j < nu && fin[j]) {
                 const double g = gval(u0 + j, p);
+                if (fabs(g) < 1.0 / 0.0) {
 #pragma unroll
-                for (int jx = 0; jx < 4; ++jx) {
-                    const double gx = g * wx[jx];
+                    for (int jx = 0; jx < 4; ++jx) {
+                        const double gx = g * wx[jx];
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
-                        atomicAdd(&gsl[j][base + jx * nq + kk], to_fixed(gx * wq[kk], fs[j]));
+                        for (int kk = 0; kk < 4; ++kk)
+                            atomicAdd(&gsl[j][base + jx * nq + kk], to_fixed(gx * wq[kk], fs[j]));
+                    }
+                } else {
+                    double *dst = a.gacc + (size_t)a.urow[u0 + j] * nodes;
+                    for (int jx = 0; jx < 4; ++jx) {
+                        const int i = ix - 1 + jx;
+                        if (i < 0 || i >= nx)
+                            continue;
+                        const double gx = g * wx0[jx];
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const int kk2 = kq - 1 + kk;
+                            if (kk2 >= 0 && kk2 < nq)
+                                unsafeAtomicAdd(&dst[i * nq + kk2], gx * wq0[kk]);
+                        }
+                    }
                 }
             }
         }

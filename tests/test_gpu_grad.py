@@ -247,13 +247,31 @@ def test_gradcheck_tiny_fp64(torch, mods, nx):
     assert torch.autograd.gradcheck(f, (v, xd, qd), eps=1e-7, atol=1e-6, rtol=1e-5)
 
 
-def test_knot_gradient_scale_range_and_nan(torch, mods):
-    """The knot sums are kept in 64-bit fixed point with a scale taken from
-    max |dL/dout|: scaling dL/dout by 1e-200 or 1e200 scales the gradient
-    alone, and a NaN in one column makes that flavour's gradient NaN and
-    leaves the others as they were."""
+def _stencil_mask(grid, x, q2):
+    """Knots (i, k) of a point's stencil: rows ix-1 .. ix+2 and global Q^2
+    columns kq-1 .. kq+2 (kq the global column of its interval), cut at the
+    axis ends; the knots an FP64 adjoint touches with the point's products."""
+    ix, s, iq, inside = oracle.locate(grid, np.array([x]), np.array([q2]))
+    assert inside[0]
+    kq = grid.q_off[s[0]] + iq[0]
+    m = np.zeros((grid.n_x, grid.n_q), dtype=bool)
+    m[max(ix[0] - 1, 0):min(ix[0] + 3, grid.n_x), max(kq - 1, 0):min(kq + 3, grid.n_q)] = True
+    return m
+
+
+@pytest.mark.parametrize("which", ["fixed_point", "fp64_atomics"])
+def test_knot_gradient_scale_range_and_nan(torch, mods, which):
+    """The knot sums of grids up to 5000 knots are kept in 64-bit fixed point
+    with a scale taken from max |dL/dout| over its finite values: scaling
+    dL/dout by 1e-200 or 1e200 scales the gradient alone.  A NaN in one
+    dL/dout entry poisons exactly that point's stencil knots of that flavour,
+    in both the fixed-point path and the FP64-atomic path of larger grids;
+    every other knot keeps the gradient of the loss without that entry."""
     api, ag = mods
-    g = cfg0_grid()
+    if which == "fixed_point":
+        g = cfg0_grid()
+    else:   # 11 x 120 x 50 = 66000 values, 6000 knots: beyond the fixed-point path
+        g = wl.make_grid(wl.config0_params(), 120, wl.Q_EDGES_PRIMARY, 50)
     pdf = api.mkPDF(g, with_values=False)
     n = 100_000
     x, q2 = wl.queries(6, n)
@@ -267,12 +285,57 @@ def test_knot_gradient_scale_range_and_nan(torch, mods):
 
     g0 = grad(w)
     big = np.abs(g0).max()
-    for s in (1e-200, 1e200):
-        gs = grad(w * s)
-        np.testing.assert_allclose(gs / s, g0, rtol=1e-9, atol=1e-9 * big)
+    if which == "fixed_point":
+        for s in (1e-200, 1e200):
+            gs = grad(w * s)
+            np.testing.assert_allclose(gs / s, g0, rtol=1e-9, atol=1e-9 * big)
+    p_nan = 1234
     wn = w.copy()
-    wn[1234, 3] = np.nan
+    wn[p_nan, 3] = np.nan
     gn = grad(wn)
-    assert np.isnan(gn[3]).all()
+    wz = w.copy()
+    wz[p_nan, 3] = 0.0
+    gz = grad(wz)
+    mask = _stencil_mask(g, x[p_nan], q2[p_nan])
+    np.testing.assert_array_equal(np.isnan(gn[3]), mask)
+    np.testing.assert_allclose(gn[3][~mask], gz[3][~mask], rtol=1e-12, atol=1e-12 * big)
     keep = [f for f in range(g0.shape[0]) if f != 3]
     np.testing.assert_allclose(gn[keep], g0[keep], rtol=1e-12, atol=1e-12 * big)
+    assert np.isfinite(gn[keep]).all()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32s"])
+def test_backward_run_to_run_spread(torch, mods, prec):
+    """Several correct results exist for the backward: its cross-workgroup
+    sums are FP64 atomics in any order.  Two runs on the same inputs agree to
+    that rounding (1e-13 of the largest knot gradient, FP64 sums of ~1e3
+    workgroup terms), and the coordinate gradients, written without atomics,
+    agree bit for bit."""
+    api, ag = mods
+    from paper_2012_08221_amd import binding as B
+    g = cfg0_grid()
+    pdf = api.mkPDF(g, with_values=False)
+    n = 1_000_000
+    x, q2 = wl.queries(7, n)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    xd, qd = torch.as_tensor(x, device="cuda"), torch.as_tensor(q2, device="cuda")
+    vals = torch.as_tensor(g.xf, device="cuda").to(dt)
+    gout = torch.as_tensor(wl.loss_weights(7, n), device="cuda").to(dt)
+    runs = []
+    for _ in range(3):
+        gv = torch.zeros_like(vals)
+        gx = torch.empty_like(xd)
+        gq = torch.empty_like(qd)
+        B.pdfx_eval_xfx_backward(pdf.handle, vals.data_ptr(), api.prec_code(prec), g.pids,
+                                 xd.data_ptr(), qd.data_ptr(), n, gout.data_ptr(), gv.data_ptr(),
+                                 gx.data_ptr(), gq.data_ptr(), B.PDFX_DOMAIN_NAN,
+                                 torch.cuda.current_stream().cuda_stream)
+        runs.append((gv.double().cpu().numpy(), gx.cpu().numpy(), gq.cpu().numpy()))
+    big = np.abs(runs[0][0]).max()
+    tol = 1e-13 if prec == "f64" else 2 ** -23
+    for r in runs[1:]:
+        spread = np.abs(r[0] - runs[0][0]).max() / big
+        print("%s knot-gradient spread %.2e of the largest" % (prec, spread))
+        assert spread <= tol
+        np.testing.assert_array_equal(r[1], runs[0][1])
+        np.testing.assert_array_equal(r[2], runs[0][2])
