@@ -31,11 +31,6 @@ namespace {
 constexpr int kStateBlock = 256;
 constexpr int kBwdBlock = 256;
 
-// flag bits
-constexpr uint8_t kOut = 1;       // outside the grid in NaN mode, or NaN input
-constexpr uint8_t kXClamp = 2;    // x clamped to the grid edge
-constexpr uint8_t kQClamp = 4;    // Q^2 clamped
-
 __global__ __launch_bounds__(kStateBlock) void state_kernel(const BwdArgs a)
 {
     extern __shared__ uint4 smem4[];
@@ -45,30 +40,36 @@ __global__ __launch_bounds__(kStateBlock) void state_kernel(const BwdArgs a)
     __syncthreads();
     const fwd::LAxis lx = fwd::lds_axis(sm, a.ax, a.lx);
     const fwd::LAxis lq = fwd::lds_axis(sm, a.aq, a.lq);
+    if (a.gacc) {
+        const int64_t nv = (int64_t)a.nf * a.nx * a.nq;
+        for (int64_t e = (int64_t)blockIdx.x * kStateBlock + threadIdx.x; e < nv;
+             e += (int64_t)gridDim.x * kStateBlock)
+            a.gacc[e] = 0.0;
+    }
     for (int64_t p = (int64_t)blockIdx.x * kStateBlock + threadIdx.x; p < a.n;
          p += (int64_t)gridDim.x * kStateBlock) {
         double xv = a.x[p], qv = a.q[p];
         uint8_t flag = 0;
         const bool nan_in = (xv != xv) || (qv != qv);
         if (nan_in) {
-            flag = kOut;
+            flag = kBwdOut;
         } else {
             const bool xin = xv >= a.ax.lo && xv <= a.ax.hi;
             const bool qin = qv >= a.aq.lo && qv <= a.aq.hi;
             if (!(xin && qin)) {
                 if (a.domain_mode == 1) {
                     if (!xin)
-                        flag |= kXClamp;
+                        flag |= kBwdXClamp;
                     if (!qin)
-                        flag |= kQClamp;
+                        flag |= kBwdQClamp;
                     xv = fmin(fmax(xv, a.ax.lo), a.ax.hi);
                     qv = fmin(fmax(qv, a.aq.lo), a.aq.hi);
                 } else {
-                    flag = kOut;
+                    flag = kBwdOut;
                 }
             }
         }
-        if (flag & kOut) {
+        if (flag & kBwdOut) {
             xv = a.ax.lo;
             qv = a.aq.lo;
         }
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(kBwdBlock) void adjoint_kernel(const BwdArgs a)
     const int64_t p_end = p_begin + a.chunk < a.n ? p_begin + a.chunk : a.n;
     for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kBwdBlock) {
         const uint8_t flag = a.st_flag[p];
-        if (flag & kOut)
+        if (flag & kBwdOut)
             continue;
         double g = 0.0;
         for (int c = c0; c < c1; ++c)
@@ -172,9 +173,9 @@ __global__ __launch_bounds__(kBwdBlock) void adjoint_kernel(const BwdArgs a)
                 du = fma(dwx[jx], r, du);
                 dw = fma(wx[jx], dr, dw);
             }
-            if (!(flag & kXClamp))
+            if (!(flag & kBwdXClamp))
                 unsafeAtomicAdd(&a.accx[p], g * du * rx[ix].inv_d);
-            if (!(flag & kQClamp))
+            if (!(flag & kBwdQClamp))
                 unsafeAtomicAdd(&a.accw[p], g * dw * rq[kq].inv_d);
         }
     }
@@ -212,11 +213,11 @@ __global__ __launch_bounds__(256) void finish_kernel(const BwdArgs a, void *grad
     if (grad_x || grad_q2) {
         for (int64_t p = t0; p < a.n; p += stride) {
             const uint8_t flag = a.st_flag[p];
-            const bool out = flag & kOut;
+            const bool out = flag & kBwdOut;
             if (grad_x)
-                grad_x[p] = out ? __builtin_nan("") : ((flag & kXClamp) ? 0.0 : a.accx[p] / a.x[p]);
+                grad_x[p] = out ? __builtin_nan("") : ((flag & kBwdXClamp) ? 0.0 : a.accx[p] / a.x[p]);
             if (grad_q2)
-                grad_q2[p] = out ? __builtin_nan("") : ((flag & kQClamp) ? 0.0 : a.accw[p] / a.q[p]);
+                grad_q2[p] = out ? __builtin_nan("") : ((flag & kBwdQClamp) ? 0.0 : a.accw[p] / a.q[p]);
         }
     }
 }
@@ -238,11 +239,12 @@ hipError_t launch_backward(const BwdArgs &a0, bool f32, void *grad_xf, double *g
 }
 
 hipError_t launch_backward_ex(const BwdArgs &a0, bool f32, void *grad_xf, double *grad_x,
-                              double *grad_q2, int cus, hipStream_t s, bool coords_ready)
+                              double *grad_q2, int cus, hipStream_t s, bool coords_done)
 {
     BwdArgs a = a0;
     hipError_t e;
-    // state pass: x and Q^2 tables in LDS
+    // state pass (x and Q^2 tables in LDS); it also zeroes the knot-gradient
+    // accumulator
     size_t off = 0;
     auto take = [&](size_t bytes, size_t align) {
         off = (off + align - 1) / align * align;
@@ -259,29 +261,29 @@ hipError_t launch_backward_ex(const BwdArgs &a0, bool f32, void *grad_xf, double
     a.lq.rec64 = take((size_t)(a.aq.n - 1) * 64, 64);
     a.lq.rec32 = a.lq.rec64;
     const size_t lds_state = off;
-    if (a.n > 0) {
+    const bool knot_pass = a.n > 0 && a.n_u > 0 && a.gacc && (coords_done || !a.accx) &&
+                           knot_grad_supported(a.nx, a.nq);
+    if (!coords_done && (a.n > 0 || a.gacc)) {
+        // without the coordinate pass the knot pass finds the maxima of
+        // |dL/dout| itself
+        a.gmax = nullptr;
         hipLaunchKernelGGL(state_kernel, dim3(grid_blocks(a.n, kStateBlock, 8 * cus)),
                            dim3(kStateBlock), lds_state, s, a);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
     }
-    // zero the accumulators
-    if (a.gacc) {
-        const int64_t nv = (int64_t)a.nf * a.nx * a.nq;
-        hipLaunchKernelGGL(zero_kernel, dim3(grid_blocks(nv, 256, 1024)), dim3(256), 0, s, a.gacc, nv);
-    }
-    if (a.accx && a.n > 0 && !coords_ready) {
+    if (a.accx && a.n > 0 && !coords_done) {
         hipLaunchKernelGGL(zero_kernel, dim3(grid_blocks(a.n, 256, 4 * cus)), dim3(256), 0, s, a.accx, a.n);
         hipLaunchKernelGGL(zero_kernel, dim3(grid_blocks(a.n, 256, 4 * cus)), dim3(256), 0, s, a.accw, a.n);
     }
     // the flavour workgroups skip the coordinate sums when they are done
     BwdArgs ka = a;
-    if (coords_ready)
+    if (coords_done)
         ka.accx = ka.accw = nullptr;
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     // adjoint pass
-    if (ka.n > 0 && ka.n_u > 0 && ka.gacc && !ka.accx && knot_grad_supported(ka.nx, ka.nq)) {
+    if (knot_pass) {
         if ((e = launch_knot_grad(ka, f32, cus, s)) != hipSuccess)
             return e;
     } else if (ka.n > 0 && ka.n_u > 0 && (ka.gacc || ka.accx)) {
@@ -313,7 +315,13 @@ hipError_t launch_backward_ex(const BwdArgs &a0, bool f32, void *grad_xf, double
             return e;
     }
     // finish
-    const int64_t work = a.n > (int64_t)a.nf * a.nx * a.nq ? a.n : (int64_t)a.nf * a.nx * a.nq;
+    if (coords_done) {
+        grad_x = grad_q2 = nullptr;
+        if (!grad_xf)
+            return hipGetLastError();
+    }
+    const int64_t nv = (int64_t)a.nf * a.nx * a.nq;
+    const int64_t work = (grad_x || grad_q2) && a.n > nv ? a.n : nv;
     if (f32)
         hipLaunchKernelGGL(finish_kernel<float>, dim3(grid_blocks(work, 256, 4 * cus)), dim3(256), 0, s,
                            a, grad_xf, grad_x, grad_q2);

@@ -7,8 +7,10 @@
 // flavour groups are staged two slabs deep by global-to-LDS copies, each
 // thread holds its point's weights, derivative weights and dL/dout values,
 // and the two sums are accumulated in registers and written once per point,
-// instead of one global atomic per point and flavour.  Arithmetic in FP64
-// whatever the values' precision.
+// instead of one global atomic per point and flavour, already divided by x
+// and Q^2 with the domain rules applied.  The pass also leaves the per-point
+// state (bins, local coordinates, flags) for the knot pass below, so that the
+// points are located once.  Arithmetic in FP64 whatever the values' precision.
 #include "bwd_internal.h"
 #include "xfx_dma_impl.h"
 #include "fixed_point.h"
@@ -71,8 +73,21 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
     const int n_req = a.n_req;
     const int n_stage = a.n_stage;
     const int64_t ntiles = (a.n + BLOCK - 1) / BLOCK;
-    if ((int64_t)blockIdx.x >= ntiles)
+    if (c.gacc)
+        for (int64_t e = (int64_t)blockIdx.x * BLOCK + tid; e < c.n_gacc;
+             e += (int64_t)gridDim.x * BLOCK)
+            c.gacc[e] = 0.0;
+    if ((int64_t)blockIdx.x >= ntiles) {
+        if (c.gmax)
+            for (int u = tid; u < a.n_u; u += BLOCK)
+                c.gmax[(size_t)blockIdx.x * a.n_u + u] = 0.0;
         return;
+    }
+    // max of finite |dL/d(slot)| over the workgroup's points, per slot
+    double gm[NSG];
+#pragma unroll
+    for (int k = 0; k < NSG; ++k)
+        gm[k] = 0.0;
 
     if (n_stage > 0)
         fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * a.gstride, nodes);
@@ -101,15 +116,35 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
         const bool more = tile + gridDim.x < ntiles;
         double xv = load_point(a.x, p, a.n);
         double qv = load_point(a.q, p, a.n);
-        fwd::domain(a, xv, qv);   // clamped or replaced; the finish pass applies the domain rule
+        const double x_in = xv, q_in = qv;   // for the chain rule
+        // flags of the domain rule, then the point clamped (CLAMP) or replaced
+        // by the lower corner (outside in NaN mode, NaN input)
+        uint8_t flag = 0;
+        {
+            const bool xin = xv >= a.ax.lo && xv <= a.ax.hi;
+            const bool qin = qv >= a.aq.lo && qv <= a.aq.hi;
+            if ((xv != xv) || (qv != qv))
+                flag = kBwdOut;
+            else if (!(xin && qin))
+                flag = a.domain_mode == 1 ? (uint8_t)((xin ? 0 : kBwdXClamp) | (qin ? 0 : kBwdQClamp))
+                                          : kBwdOut;
+        }
+        fwd::domain(a, xv, qv);
         const double lnx = log(xv), lnq = log(qv);
         const int ix = fwd::lbin(lx, xv, lnx);
         const int kq = fwd::lbin(lq, qv, lnq);
         const IntervalRec<double> rx = a.ax.rec64[ix];
         const IntervalRec<double> rq = a.aq.rec64[kq];
+        const double tx = (lnx - rx.z) * rx.inv_d, tq = (lnq - rq.z) * rq.inv_d;
+        if (c.st_idx && p < a.n) {
+            c.st_idx[p] = ix | (kq << 16);
+            c.st_flag[p] = flag;
+            c.st_tx[p] = tx;
+            c.st_tq[p] = tq;
+        }
         double wx[4], dwx[4], wq[4], dwq[4];
-        fold_both((lnx - rx.z) * rx.inv_d, rx, wx, dwx);
-        fold_both((lnq - rq.z) * rq.inv_d, rq, wq, dwq);
+        fold_both(tx, rx, wx, dwx);
+        fold_both(tq, rq, wq, dwq);
         const int base = window2(ix, nx, wx, dwx) * nq + window2(kq, nq, wq, dwq);
         // dL/d(slot) summed over the slot's output columns
         const int64_t pc = p < a.n ? p : a.n - 1;
@@ -121,6 +156,9 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
             if (k < n_stage * G && u >= 0)
                 for (int cc = a.ucol_off[u]; cc < a.ucol_off[u + 1]; ++cc)
                     gs[k] += (double)gout[pc * n_req + a.ucols[cc]];
+            const double ag = fabs(gs[k]);
+            if (ag < 1.0 / 0.0 && !(flag & kBwdOut))   // finite (false for NaN), inside
+                gm[k] = fmax(gm[k], ag);
         }
 
         fwd::wait_vm();
@@ -168,8 +206,13 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
             }
         }
         if (p < a.n) {
-            c.accx[p] = sx * rx.inv_d;
-            c.accw[p] = sw * rq.inv_d;
+            const double nan = __builtin_nan("");
+            if (c.grad_x)
+                c.grad_x[p] = (flag & kBwdOut) ? nan
+                              : (flag & kBwdXClamp) ? 0.0 : sx * rx.inv_d / x_in;
+            if (c.grad_q2)
+                c.grad_q2[p] = (flag & kBwdOut) ? nan
+                               : (flag & kBwdQClamp) ? 0.0 : sw * rq.inv_d / q_in;
         }
         // next tile's first group into slab0 once every wave is done with it
         __syncthreads();
@@ -177,35 +220,73 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
             fwd::dma_slab<BLOCK>(slab0, gsrc + (size_t)a.sgrp[0] * a.gstride, nodes);
     }
     fwd::wait_vm();
+    if (c.gmax) {
+        // the slabs are free now: slab0 holds the waves' maxima
+        double *red = reinterpret_cast<double *>(slab0);
+        const int wave = tid >> 6;
+#pragma unroll
+        for (int k = 0; k < NSG; ++k) {
+            double v = gm[k];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1)
+                v = fmax(v, __shfl_xor(v, d));
+            if ((tid & 63) == 0)
+                red[wave * NSG + k] = v;
+        }
+        __syncthreads();
+        for (int u = tid; u < a.n_u; u += BLOCK) {
+            double v = 0.0;
+            for (int k = 0; k < NSG; ++k)
+                if (a.slot_u[k] == u)
+                    for (int w = 0; w < BLOCK / 64; ++w)
+                        v = fmax(v, red[w * NSG + k]);
+            c.gmax[(size_t)blockIdx.x * a.n_u + u] = v;
+        }
+    }
 }
 
 // Knot gradient, dL/dv[f][i][k] = sum_p g[p][f] wx_i(p) wq_k(p), for up to
-// kKnotGroup flavours per workgroup: their FP64 gradient slabs (borderless)
-// sit in LDS together, so each point's state (bins, local coordinates, flags
-// from the state pass) is read and its weights folded once per group rather
-// than once per flavour.  The LDS sums are added to the FP64 accumulator at
-// the end.
+// kKnotGroup flavours per workgroup: their gradient slabs (borderless) sit in
+// LDS together, so each point's state (bins, local coordinates, flags from the
+// pass that located the points) is read and its weights folded once per group
+// rather than once per flavour.  The LDS sums are added to the FP64
+// accumulator at the end.
 //
-// The scatter is bound by LDS atomics.  A point's 16 adds go to its stencil
-// base plus offsets common to all lanes, so each wave first deals its 64
-// points out to lanes by the base's bank (wave_deal); only the point index
-// moves, and invalid points sort last and are skipped.  The sums are kept in
-// 64-bit fixed point (fixed_point.h): per flavour, a sweep over the chunk
-// finds max |dL/dout| over its finite values and the scale follows from it
-// and the axes' weight-sum bounds.  A non-finite dL/dout skips the fixed-point
-// sums: its 16 products go to the FP64 accumulator by global atomics on the
-// knots of the point's stencil (the window of knots i-1 .. i+2 cut at the
-// axis ends), so it poisons those knots only, as the FP64-atomic adjoint
-// does.
+// Each wave takes 64 consecutive points per step and loads the next step's
+// points (state and dL/dout, coalesced) before it scatters the current ones,
+// so that the loads' latency overlaps the scatter.  The interval records are
+// read from global memory (they stay in the L1 cache): the LDS is the pass's
+// bottleneck, and records staged there made it slower.  A point's 16 adds go to its stencil base plus offsets common to all
+// lanes, so the wave first deals its points out to lanes by the base's bank
+// (wave_deal) and pulls each dealt point's values from the lane that loaded
+// it.  The sums are kept in 64-bit fixed point (fixed_point.h), with the scale
+// of each flavour taken from the max of finite |dL/dout| (left per workgroup
+// by the coordinate pass, else found by a sweep over the chunk) and from the
+// axes' weight-sum bounds.  A non-finite
+// dL/dout skips the fixed-point sums: its 16 products go to the FP64
+// accumulator by global atomics on the knots of the point's stencil (the
+// window of knots i-1 .. i+2 cut at the axis ends), so it poisons those knots
+// only, as the FP64-atomic adjoint does.
 constexpr int kKnotGroup = 3;
 constexpr int kKnotBlock = 1024;
 
-__global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
+// One point as a wave step loads it (raw loads only, so that nothing waits
+// for them before the step that uses them).
+template <typename GT>
+struct KnotPt {
+    int idx;
+    unsigned int flag;
+    double tx, tq;
+    GT g[kKnotGroup];   // first column of each distinct flavour
+};
+
+template <typename GT>
+__global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
 {
     __shared__ unsigned long long gsl[kKnotGroup][kDmaNodes];
     __shared__ int khist[kKnotBlock / 64][kDealKeys];
     __shared__ double wmax[kKnotGroup + 2][kKnotBlock / 64];
-    const BwdArgs &a = k.b;
+    const GT *gout = reinterpret_cast<const GT *>(a.gout);
     const int grp = blockIdx.y;
     const int u0 = grp * kKnotGroup;
     const int nu = a.n_u - u0 < kKnotGroup ? a.n_u - u0 : kKnotGroup;
@@ -215,29 +296,34 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
             gsl[j][e] = 0ull;
     const int64_t p_begin = (int64_t)blockIdx.x * a.chunk;
     const int64_t p_end = p_begin + a.chunk < a.n ? p_begin + a.chunk : a.n;
-    auto gval = [&](int u, int64_t p) {
-        double g = 0.0;
-        for (int c = a.ucol_off[u]; c < a.ucol_off[u + 1]; ++c)
-            g += k.f32 ? (double)reinterpret_cast<const float *>(a.gout)[p * a.n_req + a.ucols[c]]
-                       : reinterpret_cast<const double *>(a.gout)[p * a.n_req + a.ucols[c]];
-        return g;
-    };
-    // m[j]: max |dL/dout| of flavour j over the chunk's points; m[kKnotGroup],
-    // m[kKnotGroup + 1]: weight-sum bounds of the x and Q^2 axes
+    // m[j]: max of finite |dL/dout| of flavour j over all points;
+    // m[kKnotGroup], m[kKnotGroup + 1]: weight-sum bounds of the x and Q^2 axes
     double m[kKnotGroup + 2];
 #pragma unroll
     for (int j = 0; j < kKnotGroup + 2; ++j)
         m[j] = 0.0;
-    for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kKnotBlock) {
-        if (a.st_flag[p] & 1)
-            continue;
+    if (a.gmax) {
+        for (int i = threadIdx.x; i < a.n_part; i += kKnotBlock)
 #pragma unroll
-        for (int j = 0; j < kKnotGroup; ++j)
-            if (j < nu) {
-                const double ag = fabs(gval(u0 + j, p));
-                if (ag < 1.0 / 0.0)   // finite (false for NaN)
-                    m[j] = fmax(m[j], ag);
-            }
+            for (int j = 0; j < kKnotGroup; ++j)
+                if (j < nu)
+                    m[j] = fmax(m[j], a.gmax[(size_t)i * a.n_u + u0 + j]);
+    } else {
+        // over the chunk's points inside the grid
+        for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kKnotBlock) {
+            if (a.st_flag[p] & kBwdOut)
+                continue;
+#pragma unroll
+            for (int j = 0; j < kKnotGroup; ++j)
+                if (j < nu) {
+                    double g = 0.0;
+                    for (int c = a.ucol_off[u0 + j]; c < a.ucol_off[u0 + j + 1]; ++c)
+                        g += (double)gout[p * a.n_req + a.ucols[c]];
+                    const double ag = fabs(g);
+                    if (ag < 1.0 / 0.0)   // finite (false for NaN)
+                        m[j] = fmax(m[j], ag);
+                }
+        }
     }
     for (int i = threadIdx.x; i < nx - 1; i += kKnotBlock)
         m[kKnotGroup] = fmax(m[kKnotGroup], weight_sum_bound(a.ax.rec64[i]));
@@ -260,57 +346,82 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
             v = nan_max(v, wmax[j][w]);
         m[j] = v;
     }
+    // the scales are the same in every lane: held in scalar registers
+    auto uniform = [](double v) {
+        const long long b = __double_as_longlong(v);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(b >> 32));
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    };
     double fs[kKnotGroup];
-    int es[kKnotGroup];
     bool fin[kKnotGroup];
+    int col[kKnotGroup];     // first output column of flavour j (clamped to a valid one)
+    bool more[kKnotGroup];   // flavour j has further columns (duplicate pids)
     bool any = false;
 #pragma unroll
     for (int j = 0; j < kKnotGroup; ++j) {
-        const double bnd = m[j] * m[kKnotGroup] * m[kKnotGroup + 1];   // |g wx wq|
-        fin[j] = bnd < 1.0 / 0.0;                                      // false for NaN
+        const double bnd = uniform(m[j] * m[kKnotGroup] * m[kKnotGroup + 1]);   // |g wx wq|
+        fin[j] = bnd < 1.0 / 0.0;                                               // false for NaN
         any = any || (j < nu && fin[j]);
-        es[j] = fin[j] ? fixed_exponent(bnd, p_end - p_begin) : 0;
-        fs[j] = ldexp(1.0, es[j]);
+        fs[j] = uniform(ldexp(1.0, fin[j] ? fixed_exponent(bnd, p_end - p_begin) : 0));
+        const int u = u0 + (j < nu ? j : nu - 1);
+        col[j] = a.ucols[a.ucol_off[u]];
+        more[j] = j < nu && a.ucol_off[u + 1] - a.ucol_off[u] > 1;
     }
     const int lane = threadIdx.x & 63;
     int *hist = khist[threadIdx.x >> 6];
-    // wave-uniform loop: every lane takes part in the reordering
-    for (int64_t p0 = p_begin + (threadIdx.x & ~63); any && p0 < p_end; p0 += kKnotBlock) {
+    // the lane's point of the step at p0 (clamped into the chunk)
+    auto load = [&](int64_t p0, KnotPt<GT> &s) {
+        const int64_t pn = p0 + lane;
+        const int64_t pc = pn < p_end ? (pn > p_begin ? pn : p_begin) : p_end - 1;
+        s.idx = a.st_idx[pc];
+        s.flag = a.st_flag[pc];
+        s.tx = a.st_tx[pc];
+        s.tq = a.st_tq[pc];
+#pragma unroll
+        for (int j = 0; j < kKnotGroup; ++j)
+            s.g[j] = gout[pc * a.n_req + col[j]];
+    };
+    // one step: the next step's points are loaded first, then the current
+    // ones are dealt and scattered
+    auto step = [&](int64_t p0, KnotPt<GT> &cur, KnotPt<GT> &nxt) {
+        load(p0 + kKnotBlock, nxt);   // unconditional (clamped), so that no wait covers it
+        const bool valid = p0 + lane < p_end && !(cur.flag & kBwdOut);
         int key = kDealKeys - 1;
-        {
-            const int64_t pn = p0 + lane;
-            const int64_t pc = pn < p_end ? pn : p_end - 1;   // clamped: a global load
-            const int idx = a.st_idx[pc];
-            if (pn < p_end && !(a.st_flag[pc] & 1)) {
-                int sx = (idx & 0xffff) - 1, sq = (idx >> 16) - 1;
-                sx = sx < 0 ? 0 : (sx > nx - 4 ? nx - 4 : sx);
-                sq = sq < 0 ? 0 : (sq > nq - 4 ? nq - 4 : sq);
-                key = (sx * nq + sq) & 31;
-            }
+        if (valid) {
+            int sx = (cur.idx & 0xffff) - 1, sq = (cur.idx >> 16) - 1;
+            sx = sx < 0 ? 0 : (sx > nx - 4 ? nx - 4 : sx);
+            sq = sq < 0 ? 0 : (sq > nq - 4 ? nq - 4 : sq);
+            key = (sx * nq + sq) & 31;
         }
-        const int64_t p = p0 + wave_deal(key, hist);
-        if (p >= p_end)
-            continue;
-        if (a.st_flag[p] & 1)   // outside the grid (NaN mode) or NaN input
-            continue;
-        const int idx = a.st_idx[p];
+        const int src = wave_deal(key, hist);
+        const bool ok = __shfl((int)valid, src) != 0;
+        const int idx = __shfl(cur.idx, src);
+        const double tx = __shfl(cur.tx, src);
+        const double tq = __shfl(cur.tq, src);
+        double gv[kKnotGroup];
+#pragma unroll
+        for (int j = 0; j < kKnotGroup; ++j)
+            gv[j] = (double)__shfl(cur.g[j], src);
+        if (!ok)   // outside the grid (NaN mode), NaN input, past the chunk
+            return;
+        const int64_t p = p0 + src;
+#pragma unroll
+        for (int j = 0; j < kKnotGroup; ++j)
+            if (more[j])
+                for (int c = a.ucol_off[u0 + j] + 1; c < a.ucol_off[u0 + j + 1]; ++c)
+                    gv[j] += (double)gout[p * a.n_req + a.ucols[c]];
         const int ix = idx & 0xffff, kq = idx >> 16;
         const IntervalRec<double> rx = a.ax.rec64[ix];
         const IntervalRec<double> rq = a.aq.rec64[kq];
         double wx[4], wq[4];
-        fwd::fold<double>(a.st_tx[p], rx.pl, rx.plql, rx.ql, rx.qr, rx.qrpr, rx.pr, wx);
-        fwd::fold<double>(a.st_tq[p], rq.pl, rq.plql, rq.ql, rq.qr, rq.qrpr, rq.pr, wq);
-        double wx0[4], wq0[4];   // weights of knots ix-1 .. ix+2, kq-1 .. kq+2
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            wx0[i] = wx[i];
-            wq0[i] = wq[i];
-        }
+        fwd::fold<double>(tx, rx.pl, rx.plql, rx.ql, rx.qr, rx.qrpr, rx.pr, wx);
+        fwd::fold<double>(tq, rq.pl, rq.plql, rq.ql, rq.qr, rq.qrpr, rq.pr, wq);
         const int base = fwd::window(ix, nx, wx) * nq + fwd::window(kq, nq, wq);
 #pragma unroll
         for (int j = 0; j < kKnotGroup; ++j) {
             if (j < nu && fin[j]) {
-                const double g = gval(u0 + j, p);
+                const double g = gv[j];
                 if (fabs(g) < 1.0 / 0.0) {
 #pragma unroll
                     for (int jx = 0; jx < 4; ++jx) {
@@ -320,26 +431,42 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const KnotArgs k)
                             atomicAdd(&gsl[j][base + jx * nq + kk], to_fixed(gx * wq[kk], fs[j]));
                     }
                 } else {
+                    // weights of knots ix-1 .. ix+2, kq-1 .. kq+2 (not shifted
+                    // into the window), folded again on this rare path
+                    double vx[4], vq[4];
+                    const IntervalRec<double> sx = a.ax.rec64[ix];
+                    const IntervalRec<double> sq = a.aq.rec64[kq];
+                    fwd::fold<double>(tx, sx.pl, sx.plql, sx.ql, sx.qr, sx.qrpr, sx.pr, vx);
+                    fwd::fold<double>(tq, sq.pl, sq.plql, sq.ql, sq.qr, sq.qrpr, sq.pr, vq);
                     double *dst = a.gacc + (size_t)a.urow[u0 + j] * nodes;
                     for (int jx = 0; jx < 4; ++jx) {
                         const int i = ix - 1 + jx;
                         if (i < 0 || i >= nx)
                             continue;
-                        const double gx = g * wx0[jx];
+                        const double gx = g * vx[jx];
                         for (int kk = 0; kk < 4; ++kk) {
                             const int kk2 = kq - 1 + kk;
                             if (kk2 >= 0 && kk2 < nq)
-                                unsafeAtomicAdd(&dst[i * nq + kk2], gx * wq0[kk]);
+                                unsafeAtomicAdd(&dst[i * nq + kk2], gx * vq[kk]);
                         }
                     }
                 }
             }
         }
+    };
+    // wave-uniform loop over the wave's steps, two register sets taken in turn
+    const int64_t pw = p_begin + (threadIdx.x & ~63);
+    KnotPt<GT> sa, sb;
+    load(pw, sa);
+    for (int64_t p0 = pw; any && p0 < p_end; p0 += 2 * kKnotBlock) {
+        step(p0, sa, sb);
+        if (p0 + kKnotBlock < p_end)
+            step(p0 + kKnotBlock, sb, sa);
     }
     __syncthreads();
     for (int j = 0; j < nu; ++j) {
         double *dst = a.gacc + (size_t)a.urow[u0 + j] * nodes;
-        const double inv = ldexp(1.0, -es[j]);
+        const double inv = 1.0 / fs[j];   // exact: a power of two
         for (int e = threadIdx.x; e < nodes; e += kKnotBlock) {
             const long long v = (long long)gsl[j][e];
             if (!fin[j])
@@ -359,26 +486,38 @@ bool knot_grad_supported(int nx, int nq)
 
 hipError_t launch_knot_grad(const BwdArgs &b, bool f32, int cus, hipStream_t s)
 {
-    KnotArgs k{b, f32 ? 1 : 0};
+    BwdArgs k = b;
     const int ngroups = (b.n_u + kKnotGroup - 1) / kKnotGroup;
     int64_t nchunk = cus / ngroups > 0 ? cus / ngroups : 1;   // one workgroup per compute unit
     int64_t chunk = (b.n + nchunk - 1) / nchunk;
     if (chunk < kKnotBlock)
         chunk = kKnotBlock;
     nchunk = (b.n + chunk - 1) / chunk;
-    k.b.chunk = (int)chunk;
-    hipLaunchKernelGGL(knot_grad_kernel, dim3((unsigned)nchunk, (unsigned)ngroups),
-                       dim3(kKnotBlock), 0, s, k);
+    k.chunk = (int)chunk;
+    if (f32)
+        hipLaunchKernelGGL(knot_grad_kernel<float>, dim3((unsigned)nchunk, (unsigned)ngroups),
+                           dim3(kKnotBlock), 0, s, k);
+    else
+        hipLaunchKernelGGL(knot_grad_kernel<double>, dim3((unsigned)nchunk, (unsigned)ngroups),
+                           dim3(kKnotBlock), 0, s, k);
     return hipGetLastError();
+}
+
+constexpr int kCoordBlock = 512;
+
+int coord_grad_blocks(int64_t n, int cus)
+{
+    const int64_t ntiles = (n + kCoordBlock - 1) / kCoordBlock;
+    int64_t grid = ntiles < cus ? ntiles : cus;   // one resident workgroup per compute unit
+    if (grid > kMaxPart)
+        grid = kMaxPart;
+    return grid < 1 ? 1 : (int)grid;
 }
 
 hipError_t launch_coord_grad(const CoordArgs &c, bool f32, int cus, hipStream_t s)
 {
-    constexpr int kBlock = 512;
-    const int64_t ntiles = (c.x.n + kBlock - 1) / kBlock;
-    int64_t grid = ntiles < cus ? ntiles : cus;   // one resident workgroup per compute unit
-    if (grid < 1)
-        grid = 1;
+    constexpr int kBlock = kCoordBlock;
+    const int grid = coord_grad_blocks(c.x.n, cus);
     auto fn = f32 ? coord_grad_kernel<float, kBlock> : coord_grad_kernel<double, kBlock>;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kBlock), 0, s, c);
     return hipGetLastError();

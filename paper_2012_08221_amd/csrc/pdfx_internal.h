@@ -148,11 +148,16 @@ struct BwdArgs {
     int64_t n;
     int domain_mode;
     const void *gout;             // [n][n_req] dL/dout, precision's type
+    int gout_f32;                 // dL/dout is FP32 (else FP64)
     int32_t *st_idx;              // per point: ix | kq << 16
     uint8_t *st_flag;             // per point: outside / x clamped / Q^2 clamped
     double *st_tx, *st_tq;        // per point: FP64 local coordinates
     double *gacc;                 // [nf][nx][nq] FP64 knot-gradient accumulator, or null
     double *accx, *accw;          // [n] FP64 sum_r g dxf/dln x, sum_r g dxf/dln Q^2, or null
+    double *gmax;                 // [n_part][n_u] per-workgroup max of finite |dL/dout| per
+                                  // distinct flavour (written by the coordinate pass), or
+                                  // null: the knot pass finds it
+    int n_part;
     int lds_recx, lds_recq, lds_grad, lds_slab;
     int chunk;                    // points per workgroup of the adjoint pass
 };

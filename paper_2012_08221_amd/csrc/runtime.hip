@@ -1129,13 +1129,15 @@ int eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec, const in
                     dma_supported(LaunchShape{512, 1}, fa.nx, fa.nq, fa.ax.nbuckets,
                                   fa.aq.nbuckets);
     }
-    // workspace: idx, flag, tx, tq, accx, accw per point + the FP64 knot accumulator
+    // workspace: idx, flag, tx, tq, accx, accw per point, the FP64 knot
+    // accumulator and the per-workgroup maxima of |dL/dout|
     const int64_t n = n_pts;
     const size_t nv = (size_t)g->nf * fa.nx * fa.nq;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t o_idx = 0, o_flag = o_idx + al(4 * n), o_tx = o_flag + al(n),
                  o_tq = o_tx + al(8 * n), o_ax = o_tq + al(8 * n), o_aw = o_ax + al(8 * n),
-                 o_g = o_aw + al(8 * n), total = o_g + al(8 * nv);
+                 o_g = o_aw + al(8 * n), o_m = o_g + al(8 * nv),
+                 total = o_m + al((size_t)8 * kMaxPart * fa.n_u);
     char *ws;
     if (fixed_ws) {
         if (total > fixed_cap)
@@ -1185,6 +1187,8 @@ int eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec, const in
     a.accx = want_coord ? (double *)(ws + o_ax) : nullptr;
     a.accw = want_coord ? (double *)(ws + o_aw) : nullptr;
     a.gacc = grad_xf ? (double *)(ws + o_g) : nullptr;
+    a.gmax = grad_xf ? (double *)(ws + o_m) : nullptr;
+    a.gout_f32 = prec == PDFX_F32S;
     if (coord_fwd) {
         ca.x.gvals = g->dvals[prec].ptr;
         ca.x.gstride = fa.nx * fa.nq;
@@ -1196,8 +1200,18 @@ int eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec, const in
             ca.x.gvals = g->scratch_dvals[prec].ptr;
         }
         ca.gout = grad_out;
-        ca.accx = a.accx;
-        ca.accw = a.accw;
+        ca.grad_x = grad_x;
+        ca.grad_q2 = grad_q2;
+        if (a.gacc) {
+            ca.st_idx = a.st_idx;
+            ca.st_flag = a.st_flag;
+            ca.st_tx = a.st_tx;
+            ca.st_tq = a.st_tq;
+            ca.gacc = a.gacc;
+            ca.n_gacc = (int64_t)nv;
+            ca.gmax = a.gmax;
+            a.n_part = coord_grad_blocks(n, g->cus);
+        }
         if ((e = launch_coord_grad(ca, prec == PDFX_F32S, g->cus, s)) != hipSuccess)
             return fail_hip(e, "adjoint launch");
     }
