@@ -24,17 +24,20 @@ namespace {
 constexpr int kExtrapBlock = 256;
 
 // Bin of v inside the axis: largest i in [0, n-2] with k[i] <= v (a value on
-// a repeated knot takes the upper copy), started from the bucket seed.
+// a repeated knot takes the upper copy), by the forward kernels' seeded search
+// over the axis' tables in global memory.
 __device__ __forceinline__ int seeded_bin(const AxisDev &ax, double v, double lnv)
 {
-    const double fb = (lnv - ax.ln_lo) * ax.inv_hb;
-    const int b = fb <= 0.0 ? 0 : (fb >= (double)(ax.nbuckets - 1) ? ax.nbuckets - 1 : (int)fb);
-    int i = ax.seed[b];
-    while (i < ax.n - 2 && ax.knots[i + 1] <= v)
-        ++i;
-    while (i > 0 && ax.knots[i] > v)
-        --i;
-    return i;
+    fwd::LAxis l;
+    l.k = ax.knots;
+    l.seed = ax.seed;
+    l.r64 = ax.rec64;
+    l.r32 = ax.rec32;
+    l.n = ax.n;
+    l.nb = ax.nbuckets;
+    l.ln_lo = ax.ln_lo;
+    l.inv_hb = ax.inv_hb;
+    return fwd::lbin(l, v, lnv);
 }
 
 // Weights of the window of bin i at v.  On a knot they are exactly one-hot,
