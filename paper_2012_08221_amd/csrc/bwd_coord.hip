@@ -252,33 +252,22 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
 // rather than once per flavour.  The LDS sums are added to the FP64
 // accumulator at the end.
 //
-// Each wave takes 64 consecutive points per step and loads the next step's
-// points (state and dL/dout, coalesced) before it scatters the current ones,
-// so that the loads' latency overlaps the scatter.  The interval records are
-// read from global memory (they stay in the L1 cache): the LDS is the pass's
-// bottleneck, and records staged there made it slower.  A point's 16 adds go to its stencil base plus offsets common to all
-// lanes, so the wave first deals its points out to lanes by the base's bank
-// (wave_deal) and pulls each dealt point's values from the lane that loaded
-// it.  The sums are kept in 64-bit fixed point (fixed_point.h), with the scale
-// of each flavour taken from the max of finite |dL/dout| (left per workgroup
-// by the coordinate pass, else found by a sweep over the chunk) and from the
-// axes' weight-sum bounds.  A non-finite
+// Each wave takes 64 consecutive points per step.  A point's 16 adds go to
+// its stencil base plus offsets common to all lanes, so the wave first deals
+// its points out to lanes by the base's bank (wave_deal); the keys for that
+// are loaded a step ahead, so that only the dealt point's own values are
+// waited for.  The interval records are read from global memory (they stay
+// in the L1 cache): the LDS is the pass's bottleneck, and records staged
+// there made it slower.  The sums are kept in 64-bit fixed point
+// (fixed_point.h), with the scale of each flavour taken from the max of
+// finite |dL/dout| (left per workgroup by the coordinate pass, else found by
+// a sweep over the chunk) and from the axes' weight-sum bounds.  A non-finite
 // dL/dout skips the fixed-point sums: its 16 products go to the FP64
 // accumulator by global atomics on the knots of the point's stencil (the
 // window of knots i-1 .. i+2 cut at the axis ends), so it poisons those knots
 // only, as the FP64-atomic adjoint does.
 constexpr int kKnotGroup = 3;
 constexpr int kKnotBlock = 1024;
-
-// One point as a wave step loads it (raw loads only, so that nothing waits
-// for them before the step that uses them).
-template <typename GT>
-struct KnotPt {
-    int idx;
-    unsigned int flag;
-    double tx, tq;
-    GT g[kKnotGroup];   // first column of each distinct flavour
-};
 
 template <typename GT>
 __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
@@ -370,47 +359,46 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
     }
     const int lane = threadIdx.x & 63;
     int *hist = khist[threadIdx.x >> 6];
-    // the lane's point of the step at p0 (clamped into the chunk)
-    auto load = [&](int64_t p0, KnotPt<GT> &s) {
+    // The keys (state of the lane's point) are loaded a step ahead; the dealt
+    // point's local coordinates and dL/dout are then read at its own index.
+    int kidx, kflag;
+    auto load_key = [&](int64_t p0, int &ki, int &kf) {
         const int64_t pn = p0 + lane;
         const int64_t pc = pn < p_end ? (pn > p_begin ? pn : p_begin) : p_end - 1;
-        s.idx = a.st_idx[pc];
-        s.flag = a.st_flag[pc];
-        s.tx = a.st_tx[pc];
-        s.tq = a.st_tq[pc];
-#pragma unroll
-        for (int j = 0; j < kKnotGroup; ++j)
-            s.g[j] = gout[pc * a.n_req + col[j]];
+        ki = a.st_idx[pc];
+        kf = a.st_flag[pc];
     };
-    // one step: the next step's points are loaded first, then the current
-    // ones are dealt and scattered
-    auto step = [&](int64_t p0, KnotPt<GT> &cur, KnotPt<GT> &nxt) {
-        load(p0 + kKnotBlock, nxt);   // unconditional (clamped), so that no wait covers it
-        const bool valid = p0 + lane < p_end && !(cur.flag & kBwdOut);
+    // wave-uniform loop: every lane takes part in the dealing
+    const int64_t pw = p_begin + (threadIdx.x & ~63);
+    load_key(pw, kidx, kflag);
+    for (int64_t p0 = pw; any && p0 < p_end; p0 += kKnotBlock) {
+        int nidx, nflag;
+        load_key(p0 + kKnotBlock, nidx, nflag);   // unconditional (clamped): no wait covers it
+        const bool valid = p0 + lane < p_end && !(kflag & kBwdOut);
         int key = kDealKeys - 1;
         if (valid) {
-            int sx = (cur.idx & 0xffff) - 1, sq = (cur.idx >> 16) - 1;
+            int sx = (kidx & 0xffff) - 1, sq = (kidx >> 16) - 1;
             sx = sx < 0 ? 0 : (sx > nx - 4 ? nx - 4 : sx);
             sq = sq < 0 ? 0 : (sq > nq - 4 ? nq - 4 : sq);
             key = (sx * nq + sq) & 31;
         }
         const int src = wave_deal(key, hist);
         const bool ok = __shfl((int)valid, src) != 0;
-        const int idx = __shfl(cur.idx, src);
-        const double tx = __shfl(cur.tx, src);
-        const double tq = __shfl(cur.tq, src);
+        const int idx = __shfl(kidx, src);
+        kidx = nidx;
+        kflag = nflag;
+        if (!ok)   // outside the grid (NaN mode), NaN input, past the chunk
+            continue;
+        const int64_t p = p0 + src;
+        const double tx = a.st_tx[p], tq = a.st_tq[p];
         double gv[kKnotGroup];
 #pragma unroll
-        for (int j = 0; j < kKnotGroup; ++j)
-            gv[j] = (double)__shfl(cur.g[j], src);
-        if (!ok)   // outside the grid (NaN mode), NaN input, past the chunk
-            return;
-        const int64_t p = p0 + src;
-#pragma unroll
-        for (int j = 0; j < kKnotGroup; ++j)
+        for (int j = 0; j < kKnotGroup; ++j) {
+            gv[j] = (double)gout[p * a.n_req + col[j]];
             if (more[j])
                 for (int c = a.ucol_off[u0 + j] + 1; c < a.ucol_off[u0 + j + 1]; ++c)
                     gv[j] += (double)gout[p * a.n_req + a.ucols[c]];
+        }
         const int ix = idx & 0xffff, kq = idx >> 16;
         const IntervalRec<double> rx = a.ax.rec64[ix];
         const IntervalRec<double> rq = a.aq.rec64[kq];
@@ -453,15 +441,6 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
                 }
             }
         }
-    };
-    // wave-uniform loop over the wave's steps, two register sets taken in turn
-    const int64_t pw = p_begin + (threadIdx.x & ~63);
-    KnotPt<GT> sa, sb;
-    load(pw, sa);
-    for (int64_t p0 = pw; any && p0 < p_end; p0 += 2 * kKnotBlock) {
-        step(p0, sa, sb);
-        if (p0 + kKnotBlock < p_end)
-            step(p0 + kKnotBlock, sb, sa);
     }
     __syncthreads();
     for (int j = 0; j < nu; ++j) {
