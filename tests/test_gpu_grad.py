@@ -339,3 +339,60 @@ def test_backward_run_to_run_spread(torch, mods, prec):
         assert spread <= tol
         np.testing.assert_array_equal(r[1], runs[0][1])
         np.testing.assert_array_equal(r[2], runs[0][2])
+
+
+@pytest.mark.parametrize("prec_name", ["f64", "f32s"])
+def test_knot_gradient_repeated_and_absent_pids(torch, mods, prec_name):
+    """A request with a repeated pid and one the grid lacks has the knot
+    gradient of its distinct pids with the repeated columns' dL/dout summed,
+    whether the coordinate pass runs first (it leaves the |dL/dout| maxima)
+    or the knot pass finds them itself; its coordinate gradients equal those of
+    the distinct request bit for bit.  dL/dout values are multiples of 1/4 of
+    magnitude at most 8, so the summed column is exact in FP32 too."""
+    api, _ = mods
+    from paper_2012_08221_amd import binding as B
+    g = cfg0_grid()
+    pdf = api.mkPDF(g)
+    prec = B.PDFX_F64 if prec_name == "f64" else B.PDFX_F32S
+    dt = torch.float64 if prec == B.PDFX_F64 else torch.float32
+    n = 300_001
+    x_np, q2_np = wl.queries(71, n)
+    x_np[::997] = 1e-12                                   # outside: NaN coordinate gradients
+    x = torch.as_tensor(x_np, device="cuda")
+    q2 = torch.as_tensor(q2_np, device="cuda")
+    cols = np.random.default_rng(71).integers(-32, 33, size=(n, 5)) / 4.0
+    req = [21, 2, 2, 7, 1]                                # pid 7 is not in the grid
+    dist = [21, 2, 1]
+    summed = np.stack([cols[:, 0], cols[:, 1] + cols[:, 2], cols[:, 4]], axis=1)
+    go_req = torch.as_tensor(cols, device="cuda").to(dt).contiguous()
+    go_dist = torch.as_tensor(summed, device="cuda").to(dt).contiguous()
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run(pids, gout, coords):
+        gv = torch.zeros(pdf.shape, dtype=dt, device="cuda")
+        gx = torch.full_like(x, -1.0)
+        gq = torch.full_like(q2, -1.0)
+        B.pdfx_eval_xfx_backward(pdf.handle, None, prec, pids, x.data_ptr(), q2.data_ptr(), n,
+                                 gout.data_ptr(), gv.data_ptr(),
+                                 gx.data_ptr() if coords else None,
+                                 gq.data_ptr() if coords else None,
+                                 B.PDFX_DOMAIN_NAN, stream)
+        torch.cuda.synchronize()
+        return gv.double().cpu().numpy(), gx.cpu().numpy(), gq.cpu().numpy()
+
+    ref, rx, rq = run(dist, go_dist, True)
+    rows = [int(np.where(g.pids == p)[0][0]) for p in dist]
+    others = [r for r in range(len(g.pids)) if r not in rows]
+    assert np.abs(ref[rows]).max(axis=(1, 2)).min() > 0
+    assert not ref[others].any()
+    tol = 1e-10 if prec == B.PDFX_F64 else 2e-7
+    scale = np.abs(ref).max(axis=(1, 2), keepdims=True) + 1e-300
+    for pids, gout, coords in ((req, go_req, True), (req, go_req, False), (dist, go_dist, False)):
+        gv, gx, gq = run(pids, gout, coords)
+        assert np.all(np.abs(gv - ref) <= tol * scale), (pids, coords)
+        if coords:
+            np.testing.assert_array_equal(gx, rx)
+            np.testing.assert_array_equal(gq, rq)
+        else:
+            assert (gx == -1.0).all() and (gq == -1.0).all()
+    assert np.isnan(rx[::997]).all() and np.isfinite(rx[1::997]).all()
