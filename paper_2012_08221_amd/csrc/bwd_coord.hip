@@ -111,11 +111,36 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
     lq.ln_lo = a.aq.ln_lo;
     lq.inv_hb = a.aq.inv_hb;
 
+    // A point's coordinates and the first dL/dout column of each slot's
+    // flavour are loaded a tile ahead (clamped to the last point), during the
+    // first stage of the tile before, so that the location of a tile does not
+    // wait for them; further columns of a repeated pid are read when the tile
+    // starts.
+    const int n_slot = n_stage * G;
+    bool dup_cols = false;
+    for (int k = 0; k < n_slot; ++k)
+        dup_cols = dup_cols || (a.slot_u[k] >= 0 &&
+                                a.ucol_off[a.slot_u[k] + 1] - a.ucol_off[a.slot_u[k]] > 1);
+    auto load_pt = [&](int64_t p, double &xv, double &qv, V (&g1)[NSG]) {
+        xv = load_point(a.x, p, a.n);
+        qv = load_point(a.q, p, a.n);
+        const int64_t pc = p < a.n ? p : a.n - 1;
+#pragma unroll
+        for (int k = 0; k < NSG; ++k)
+            if (k < n_slot && a.slot_col[k] >= 0)
+                g1[k] = gout[pc * n_req + a.slot_col[k]];
+    };
+    double x_pt, q_pt;
+    V g_pt[NSG];
+#pragma unroll
+    for (int k = 0; k < NSG; ++k)
+        g_pt[k] = V(0);   // slots never loaded stay 0
+    load_pt((int64_t)blockIdx.x * BLOCK + tid, x_pt, q_pt, g_pt);
+
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t p = tile * BLOCK + tid;
         const bool more = tile + gridDim.x < ntiles;
-        double xv = load_point(a.x, p, a.n);
-        double qv = load_point(a.q, p, a.n);
+        double xv = x_pt, qv = q_pt;
         const double x_in = xv, q_in = qv;   // for the chain rule
         // flags of the domain rule, then the point clamped (CLAMP) or replaced
         // by the lower corner (outside in NaN mode, NaN input)
@@ -146,16 +171,24 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
         fold_both(tx, rx, wx, dwx);
         fold_both(tq, rq, wq, dwq);
         const int base = window2(ix, nx, wx, dwx) * nq + window2(kq, nq, wq, dwq);
-        // dL/d(slot) summed over the slot's output columns
-        const int64_t pc = p < a.n ? p : a.n - 1;
+        // dL/d(slot) summed over the slot's output columns (0 for slots that
+        // hold no requested flavour)
         double gs[NSG];
 #pragma unroll
+        for (int k = 0; k < NSG; ++k)
+            gs[k] = (double)g_pt[k];
+        if (dup_cols) {
+            const int64_t pc = p < a.n ? p : a.n - 1;
+#pragma unroll
+            for (int k = 0; k < NSG; ++k) {
+                const int u = a.slot_u[k];
+                if (k < n_slot && u >= 0)
+                    for (int cc = a.ucol_off[u] + 1; cc < a.ucol_off[u + 1]; ++cc)
+                        gs[k] += (double)gout[pc * n_req + a.ucols[cc]];
+            }
+        }
+#pragma unroll
         for (int k = 0; k < NSG; ++k) {
-            gs[k] = 0.0;
-            const int u = a.slot_u[k];
-            if (k < n_stage * G && u >= 0)
-                for (int cc = a.ucol_off[u]; cc < a.ucol_off[u + 1]; ++cc)
-                    gs[k] += (double)gout[pc * n_req + a.ucols[cc]];
             const double ag = fabs(gs[k]);
             if (ag < 1.0 / 0.0 && !(flag & kBwdOut))   // finite (false for NaN), inside
                 gm[k] = fmax(gm[k], ag);
@@ -172,6 +205,10 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
                 uint4 *const nxt = (s & 1) ? slab0 : slab1;
                 if (!last)
                     fwd::dma_slab<BLOCK>(nxt, gsrc + (size_t)a.sgrp[s + 1] * a.gstride, nodes);
+                // the next tile's point: its loads land while this stage's
+                // gathers run (every later wait for a slab copy covers them)
+                if (s == 0)
+                    load_pt(p + (int64_t)gridDim.x * BLOCK, x_pt, q_pt, g_pt);
                 double du[G], dw[G];
 #pragma unroll
                 for (int jx = 0; jx < 4; ++jx) {
