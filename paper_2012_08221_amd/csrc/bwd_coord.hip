@@ -322,6 +322,26 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
             gsl[j][e] = 0ull;
     const int64_t p_begin = (int64_t)blockIdx.x * a.chunk;
     const int64_t p_end = p_begin + a.chunk < a.n ? p_begin + a.chunk : a.n;
+    int col[kKnotGroup];     // first output column of flavour j (clamped to a valid one)
+    bool more[kKnotGroup];   // flavour j has further columns (duplicate pids)
+#pragma unroll
+    for (int j = 0; j < kKnotGroup; ++j) {
+        const int u = u0 + (j < nu ? j : nu - 1);
+        col[j] = a.ucols[a.ucol_off[u]];
+        more[j] = j < nu && a.ucol_off[u + 1] - a.ucol_off[u] > 1;
+    }
+    // dL/dout of the group's flavours at point p, each summed over its columns
+    // (the first columns loaded together, so that their latencies overlap)
+    auto gsum = [&](int64_t p, double (&g)[kKnotGroup]) {
+#pragma unroll
+        for (int j = 0; j < kKnotGroup; ++j)
+            g[j] = (double)gout[p * a.n_req + col[j]];
+#pragma unroll
+        for (int j = 0; j < kKnotGroup; ++j)
+            if (more[j])
+                for (int c = a.ucol_off[u0 + j] + 1; c < a.ucol_off[u0 + j + 1]; ++c)
+                    g[j] += (double)gout[p * a.n_req + a.ucols[c]];
+    };
     // m[j]: max of finite |dL/dout| of flavour j over all points;
     // m[kKnotGroup], m[kKnotGroup + 1]: weight-sum bounds of the x and Q^2 axes
     double m[kKnotGroup + 2];
@@ -337,18 +357,15 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
     } else {
         // over the chunk's points inside the grid
         for (int64_t p = p_begin + threadIdx.x; p < p_end; p += kKnotBlock) {
-            if (a.st_flag[p] & kBwdOut)
-                continue;
+            const bool in = !(a.st_flag[p] & kBwdOut);
+            double g[kKnotGroup];
+            gsum(p, g);
 #pragma unroll
-            for (int j = 0; j < kKnotGroup; ++j)
-                if (j < nu) {
-                    double g = 0.0;
-                    for (int c = a.ucol_off[u0 + j]; c < a.ucol_off[u0 + j + 1]; ++c)
-                        g += (double)gout[p * a.n_req + a.ucols[c]];
-                    const double ag = fabs(g);
-                    if (ag < 1.0 / 0.0)   // finite (false for NaN)
-                        m[j] = fmax(m[j], ag);
-                }
+            for (int j = 0; j < kKnotGroup; ++j) {
+                const double ag = fabs(g[j]);
+                if (in && j < nu && ag < 1.0 / 0.0)   // finite (false for NaN)
+                    m[j] = fmax(m[j], ag);
+            }
         }
     }
     for (int i = threadIdx.x; i < nx - 1; i += kKnotBlock)
@@ -381,8 +398,6 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
     };
     double fs[kKnotGroup];
     bool fin[kKnotGroup];
-    int col[kKnotGroup];     // first output column of flavour j (clamped to a valid one)
-    bool more[kKnotGroup];   // flavour j has further columns (duplicate pids)
     bool any = false;
 #pragma unroll
     for (int j = 0; j < kKnotGroup; ++j) {
@@ -390,9 +405,6 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
         fin[j] = bnd < 1.0 / 0.0;                                               // false for NaN
         any = any || (j < nu && fin[j]);
         fs[j] = uniform(ldexp(1.0, fin[j] ? fixed_exponent(bnd, p_end - p_begin) : 0));
-        const int u = u0 + (j < nu ? j : nu - 1);
-        col[j] = a.ucols[a.ucol_off[u]];
-        more[j] = j < nu && a.ucol_off[u + 1] - a.ucol_off[u] > 1;
     }
     const int lane = threadIdx.x & 63;
     int *hist = khist[threadIdx.x >> 6];
@@ -429,13 +441,7 @@ __global__ __launch_bounds__(kKnotBlock) void knot_grad_kernel(const BwdArgs a)
         const int64_t p = p0 + src;
         const double tx = a.st_tx[p], tq = a.st_tq[p];
         double gv[kKnotGroup];
-#pragma unroll
-        for (int j = 0; j < kKnotGroup; ++j) {
-            gv[j] = (double)gout[p * a.n_req + col[j]];
-            if (more[j])
-                for (int c = a.ucol_off[u0 + j] + 1; c < a.ucol_off[u0 + j + 1]; ++c)
-                    gv[j] += (double)gout[p * a.n_req + a.ucols[c]];
-        }
+        gsum(p, gv);
         const int ix = idx & 0xffff, kq = idx >> 16;
         const IntervalRec<double> rx = a.ax.rec64[ix];
         const IntervalRec<double> rq = a.aq.rec64[kq];
