@@ -390,35 +390,42 @@ __global__ __launch_bounds__(kPairBlock) void dy_pair_adjoint_kernel(const DyArg
     const double f_q = ldexp(1.0, e_q), f_qb = ldexp(1.0, e_qb);
     const int lane = threadIdx.x & 63;
     int *hist = khist[threadIdx.x >> 6];
+    // The keys (each lane's quark bins) are loaded one wave step ahead; the
+    // dealt point's state is then read at its own index, all at once.
+    auto load_key = [&](int64_t p0) {
+        const int64_t pn = p0 + lane;
+        return a.st_i1[pn < p_end ? (pn > p_begin ? pn : p_begin) : p_end - 1];
+    };
     // wave-uniform loop: every lane takes part in the dealing
-    for (int64_t p0 = p_begin + (threadIdx.x & ~63); finite && p0 < p_end; p0 += kPairBlock) {
+    const int64_t pw = p_begin + (threadIdx.x & ~63);
+    int kidx = load_key(pw);
+    for (int64_t p0 = pw; finite && p0 < p_end; p0 += kPairBlock) {
+        const int nidx = load_key(p0 + kPairBlock);   // unconditional (clamped): no wait covers it
+        const bool valid = p0 + lane < p_end && kidx >= 0;
         int key = kDealKeys - 1;
-        {
-            const int64_t pn = p0 + lane;
-            const int64_t pc = pn < p_end ? pn : p_end - 1;   // clamped: a global load
-            const int idx = a.st_i1[pc];
-            if (pn < p_end && idx >= 0) {
-                int sx = (idx & 0xffff) - 1, sq = (idx >> 16) - 1;
-                sx = sx < 0 ? 0 : (sx > nx - 4 ? nx - 4 : sx);
-                sq = sq < 0 ? 0 : (sq > nq - 4 ? nq - 4 : sq);
-                key = (sx * nq + sq) & 31;
-            }
+        if (valid) {
+            int sx = (kidx & 0xffff) - 1, sq = (kidx >> 16) - 1;
+            sx = sx < 0 ? 0 : (sx > nx - 4 ? nx - 4 : sx);
+            sq = sq < 0 ? 0 : (sq > nq - 4 ? nq - 4 : sq);
+            key = (sx * nq + sq) & 31;
         }
-        const int64_t p = p0 + wave_deal(key, hist);
-        if (p >= p_end)
+        const int src = wave_deal(key, hist);
+        const bool ok = __shfl((int)valid, src) != 0;
+        const int idx1 = __shfl(kidx, src);
+        kidx = nidx;
+        if (!ok)   // outside the grid, or past the chunk
             continue;
-        const int idx1 = a.st_i1[p];
-        if (idx1 < 0)
-            continue;
+        const int64_t p = p0 + src;
         const int i1 = idx1 & 0xffff, kq = idx1 >> 16, i2 = a.st_i2[p];
+        const double t1 = a.st_t1[p], t2 = a.st_t2[p], tq = a.st_tq[p], as = a.st_as[p];
         double w1[4], w2[4], wq[4];
         {
             const IntervalRec<double> r1 = a.ax.rec64[i1];
             const IntervalRec<double> r2 = a.ax.rec64[i2];
             const IntervalRec<double> rr = a.aq.rec64[kq];
-            fwd::fold<double>(a.st_t1[p], r1.pl, r1.plql, r1.ql, r1.qr, r1.qrpr, r1.pr, w1);
-            fwd::fold<double>(a.st_t2[p], r2.pl, r2.plql, r2.ql, r2.qr, r2.qrpr, r2.pr, w2);
-            fwd::fold<double>(a.st_tq[p], rr.pl, rr.plql, rr.ql, rr.qr, rr.qrpr, rr.pr, wq);
+            fwd::fold<double>(t1, r1.pl, r1.plql, r1.ql, r1.qr, r1.qrpr, r1.pr, w1);
+            fwd::fold<double>(t2, r2.pl, r2.plql, r2.ql, r2.qr, r2.qrpr, r2.pr, w2);
+            fwd::fold<double>(tq, rr.pl, rr.plql, rr.ql, rr.qr, rr.qrpr, rr.pr, wq);
         }
         const int cq = fwd::window(kq, nq, wq);
         const int b1 = fwd::window(i1, nx, w1) * nq + cq;
@@ -436,7 +443,7 @@ __global__ __launch_bounds__(kPairBlock) void dy_pair_adjoint_kernel(const DyArg
             f1 = fma(w1[jx], r1, f1);
             f2 = fma(w2[jx], r2, f2);
         }
-        const double c = a.scale * a.L2 * a.st_as[p];
+        const double c = a.scale * a.L2 * as;
         const double mq = c * f2, mqb = c * f1;
 #pragma unroll
         for (int jx = 0; jx < 4; ++jx) {
