@@ -46,9 +46,17 @@ __global__ __launch_bounds__(kStateBlock) void state_kernel(const BwdArgs a)
              e += (int64_t)gridDim.x * kStateBlock)
             a.gacc[e] = 0.0;
     }
-    for (int64_t p = (int64_t)blockIdx.x * kStateBlock + threadIdx.x; p < a.n;
-         p += (int64_t)gridDim.x * kStateBlock) {
-        double xv = a.x[p], qv = a.q[p];
+    // each thread's next point is loaded one iteration ahead (clamped to the
+    // last point), so that no iteration waits for its own
+    const int64_t stride = (int64_t)gridDim.x * kStateBlock;
+    int64_t p = (int64_t)blockIdx.x * kStateBlock + threadIdx.x;
+    double xn = a.n > 0 ? a.x[p < a.n ? p : a.n - 1] : 0.0;
+    double qn = a.n > 0 ? a.q[p < a.n ? p : a.n - 1] : 0.0;
+    for (; p < a.n; p += stride) {
+        double xv = xn, qv = qn;
+        const int64_t pn = p + stride < a.n ? p + stride : a.n - 1;
+        xn = a.x[pn];
+        qn = a.q[pn];
         uint8_t flag = 0;
         const bool nan_in = (xv != xv) || (qv != qv);
         if (nan_in) {

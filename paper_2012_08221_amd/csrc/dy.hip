@@ -209,12 +209,21 @@ __global__ __launch_bounds__(256) void dy_state_kernel(const DyArgs a)
     const fwd::LAxis lq = fwd::lds_axis(sm, a.aq, a.lq);
     const fwd::LAxis la = fwd::lds_axis(sm, a.aa, a.la);
     const double *asv = reinterpret_cast<const double *>(sm + a.lds_asv);
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < a.n;
-         p += (int64_t)gridDim.x * 256) {
+    // each thread's next point's uniforms are loaded one iteration ahead
+    // (clamped to the last point), so that no iteration waits for its own
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p0 = p < a.n ? p : a.n - 1;   // launched with n > 0 only
+    double u1n = a.u1[p0], u2n = a.u2[p0];
+    for (; p < a.n; p += stride) {
+        const double u1 = u1n, u2 = u2n;
+        const int64_t pn = p + stride < a.n ? p + stride : a.n - 1;
+        u1n = a.u1[pn];
+        u2n = a.u2[pn];
         // ln x is the exponent itself (the bins compare raw x, so a last-bit
         // difference from log(x) cannot change them)
-        double lnx1 = a.lnxmin + a.u1[p] * a.lnrange;
-        double lnx2 = a.lnxmin + a.u2[p] * a.lnrange;
+        double lnx1 = a.lnxmin + u1 * a.lnrange;
+        double lnx2 = a.lnxmin + u2 * a.lnrange;
         double x1 = exp(lnx1);
         double x2 = exp(lnx2);
         double q2 = x1 * x2 * a.s;
