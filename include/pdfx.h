@@ -212,7 +212,8 @@ int pdfx_eval_xfx_backward(const pdfx_grid *g, const void *xf_dev, int prec,
  * a fixed device array of PDFX_NOALLOC_SCRATCH_BYTES per GPU, held until the
  * process ends, so the call allocates nothing.  It needs
  * 256-byte-rounded n_pts * (4 + 1 + 4 * 8) bytes plus 8 * n_flav * n_x * n_q
- * (about 1.3e6 points on an 11 x 100 x 50 grid); a larger call returns
+ * plus 8 * 1024 per distinct requested flavour (about 1.3e6 points on an
+ * 11 x 100 x 50 grid); a larger call returns
  * PDFX_EINVAL before enqueuing anything.  All calls on one GPU share that
  * array: calls that may overlap on one GPU (other streams or host threads)
  * race, so order them on one stream. */
