@@ -194,6 +194,8 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
                 gm[k] = fmax(gm[k], ag);
         }
 
+        if (n_stage == 0)   // no stage to load the next point in (no pid of the grid requested)
+            load_pt(p + (int64_t)gridDim.x * BLOCK, x_pt, q_pt, g_pt);
         fwd::wait_vm();
         __syncthreads();   // the tile's first group has landed
         double sx = 0.0, sw = 0.0;

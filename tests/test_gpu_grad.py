@@ -396,3 +396,33 @@ def test_knot_gradient_repeated_and_absent_pids(torch, mods, prec_name):
         else:
             assert (gx == -1.0).all() and (gq == -1.0).all()
     assert np.isnan(rx[::997]).all() and np.isfinite(rx[1::997]).all()
+
+
+def test_backward_of_a_request_the_grid_lacks(torch, mods):
+    """pids the grid does not hold give zero columns, so every gradient of
+    them is zero, except NaN coordinate gradients at points outside the grid
+    (NaN mode); the coordinate pass then has no flavour group to stage and
+    must still step through every tile's own points."""
+    api, _ = mods
+    from paper_2012_08221_amd import binding as B
+    g = cfg0_grid()
+    pdf = api.mkPDF(g)
+    n = 300_001
+    x_np, q2_np = wl.queries(73, n)
+    x_np[::997] = 1e-12
+    x = torch.as_tensor(x_np, device="cuda")
+    q2 = torch.as_tensor(q2_np, device="cuda")
+    gout = torch.ones((n, 2), dtype=torch.float64, device="cuda")
+    gv = torch.full(pdf.shape, 0.5, dtype=torch.float64, device="cuda")
+    gx = torch.full_like(x, -1.0)
+    gq = torch.full_like(q2, -1.0)
+    B.pdfx_eval_xfx_backward(pdf.handle, None, B.PDFX_F64, [7, 8], x.data_ptr(), q2.data_ptr(), n,
+                             gout.data_ptr(), gv.data_ptr(), gx.data_ptr(), gq.data_ptr(),
+                             B.PDFX_DOMAIN_NAN, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    out = np.zeros(n, bool)
+    out[::997] = True
+    gx, gq = gx.cpu().numpy(), gq.cpu().numpy()
+    assert np.isnan(gx[out]).all() and np.isnan(gq[out]).all()
+    assert (gx[~out] == 0.0).all() and (gq[~out] == 0.0).all()
+    assert (gv.cpu().numpy() == 0.5).all()                # grad_xf accumulates nothing
