@@ -8,10 +8,13 @@
 // 1/d_i).  The knot gradient does not depend on the values (the map is linear
 // in them).
 //
-// Three launches:
+// Grids that fit the double-buffered layout take the coordinate pass and the
+// knot pass of bwd_coord.hip; the coordinate pass then leaves the per-point
+// state itself, and only the finish below runs after them.  The passes here:
 //   state:  per point, bins (ix, kq), FP64 local coordinates (tx, tq) and
-//           flags; the logs and searches run once per point.
-//   adjoint: grid = (point chunk, distinct flavour).  The workgroup rebuilds
+//           flags; the logs and searches run once per point.  It also zeroes
+//           the FP64 knot accumulator.
+//   adjoint (larger grids): grid = (point chunk, distinct flavour).  The workgroup rebuilds
 //           the FP64 weights and derivative weights from the state, scatters
 //           g * wx_j * wq_k into an FP64 gradient slab in LDS (ds_add_f64) and,
 //           with the value slab staged in LDS, accumulates g * dxf/dln x and
