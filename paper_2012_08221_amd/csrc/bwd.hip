@@ -243,12 +243,6 @@ int grid_blocks(int64_t n, int block, int cap)
 
 }  // namespace
 
-hipError_t launch_backward(const BwdArgs &a0, bool f32, void *grad_xf, double *grad_x,
-                           double *grad_q2, int cus, hipStream_t s)
-{
-    return launch_backward_ex(a0, f32, grad_xf, grad_x, grad_q2, cus, s, false);
-}
-
 hipError_t launch_backward_ex(const BwdArgs &a0, bool f32, void *grad_xf, double *grad_x,
                               double *grad_q2, int cus, hipStream_t s, bool coords_done)
 {

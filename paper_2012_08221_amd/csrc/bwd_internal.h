@@ -45,7 +45,8 @@ hipError_t launch_coord_grad(const CoordArgs &c, bool f32, int cus, hipStream_t 
 bool knot_grad_supported(int nx, int nq);
 hipError_t launch_knot_grad(const BwdArgs &b, bool f32, int cus, hipStream_t s);
 
-// The adjoint as launch_backward, except that with coords_done the
+// The adjoint after the argument checks: state pass, knot pass (or the
+// per-flavour scatter for grids beyond it) and finish.  With coords_done the
 // coordinate gradients are already written (launch_coord_grad), and, when a
 // knot gradient is wanted, so are the per-point state and the zeroed gacc:
 // only the knot pass and the finish of grad_xf remain.

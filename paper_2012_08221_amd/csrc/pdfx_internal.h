@@ -274,8 +274,6 @@ bool dma_supported(LaunchShape ls, int nx, int nq, int nbx, int nbq, bool f32 = 
 bool dma_alphas_fit(int nx, int nq, bool f32);
 hipError_t launch_alphas(const AlphasArgs &a, bool f32, hipStream_t s);
 hipError_t launch_repack(const RepackArgs &a, bool f32, hipStream_t s);
-hipError_t launch_backward(const BwdArgs &a, bool f32, void *grad_xf, double *grad_x,
-                           double *grad_q2, int cus, hipStream_t s);
 hipError_t launch_set(const SetArgs &a, bool f32, LaunchShape ls, size_t lds, int cus, hipStream_t s);
 hipError_t launch_dy_forward(const DyArgs &a, bool f32, int cus, hipStream_t s, int *n_blocks);
 hipError_t launch_dy_backward(const DyArgs &a, bool f32, void *grad_xf, int cus, hipStream_t s);
