@@ -56,13 +56,16 @@ __device__ __forceinline__ int wave_deal(int key, int *hist)
     const int lrank = atomicAdd(&hist[key], 1);   // rank among the wave's equal keys
     __builtin_amdgcn_wave_barrier();
     const int cnt = lane < kDealKeys ? hist[lane] : 0;
+    // inclusive scan over the 64 lanes by DPP (VALU only, leaving the LDS pipe
+    // to the scatter): shifts within each 16-lane row, then the last lane of
+    // row 0 (of row 2) added to row 1 (row 3), then lane 31 to rows 2 and 3
     int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int t = __shfl_up(incl, d);
-        if (lane >= d)
-            incl += t;
-    }
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, true);   // row_shr:1
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, true);   // row_shr:2
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, true);   // row_shr:4
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xf, 0xf, true);   // row_shr:8
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x143, 0xc, 0xf, false);  // row_bcast:31
     const int rank = __shfl(incl - cnt, key) + lrank;
     const int dest = (rank & 3) * 16 + (rank >> 2);
     return __builtin_amdgcn_ds_permute(dest * 4, lane);
