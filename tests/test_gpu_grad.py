@@ -426,3 +426,73 @@ def test_backward_of_a_request_the_grid_lacks(torch, mods):
     assert np.isnan(gx[out]).all() and np.isnan(gq[out]).all()
     assert (gx[~out] == 0.0).all() and (gq[~out] == 0.0).all()
     assert (gv.cpu().numpy() == 0.5).all()                # grad_xf accumulates nothing
+
+
+@pytest.mark.parametrize("prec_name", ["f64", "f32s"])
+@pytest.mark.parametrize("n", [0, 1, 63, 1025, 4097])
+def test_backward_ragged_sizes(torch, mods, prec_name, n):
+    """Empty and ragged batches through the C ABI: nothing is written for n = 0;
+    otherwise the adjoint of the batch equals the sum of the adjoints of its
+    two halves (it is a sum over points), the coordinate gradients bit for
+    bit, and at n = 63 the knot gradient matches the oracle's central
+    differences on the knots the points touch."""
+    api, _ = mods
+    from paper_2012_08221_amd import binding as B
+    g = cfg0_grid()
+    pdf = api.mkPDF(g)
+    prec = B.PDFX_F64 if prec_name == "f64" else B.PDFX_F32S
+    dt = torch.float64 if prec == B.PDFX_F64 else torch.float32
+    x_np, q2_np = wl.queries(75, max(n, 1))
+    x_np, q2_np = x_np[:n], q2_np[:n]
+    w_np = wl.loss_weights(75, max(n, 1))[:n]
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run(lo, hi):
+        m = hi - lo
+        x = torch.as_tensor(x_np[lo:hi].copy(), device="cuda")
+        q2 = torch.as_tensor(q2_np[lo:hi].copy(), device="cuda")
+        go = torch.as_tensor(w_np[lo:hi].copy(), device="cuda").to(dt).contiguous()
+        gv = torch.zeros(pdf.shape, dtype=dt, device="cuda")
+        gx = torch.full((m + 1,), -1.0, dtype=torch.float64, device="cuda")   # one guard element
+        gq = torch.full((m + 1,), -1.0, dtype=torch.float64, device="cuda")
+        B.pdfx_eval_xfx_backward(pdf.handle, None, prec, [int(p) for p in g.pids],
+                                 x.data_ptr(), q2.data_ptr(), m, go.data_ptr(), gv.data_ptr(),
+                                 gx.data_ptr(), gq.data_ptr(), B.PDFX_DOMAIN_NAN, stream)
+        torch.cuda.synchronize()
+        return gv.double().cpu().numpy(), gx.cpu().numpy(), gq.cpu().numpy()
+
+    gv, gx, gq = run(0, n)
+    assert gx[n] == -1.0 and gq[n] == -1.0                 # nothing written past the batch
+    if n == 0:
+        assert not gv.any()
+        return
+    assert np.isfinite(gx[:n]).all() and np.isfinite(gq[:n]).all()
+    h = n // 2
+    a = run(0, h)
+    b = run(h, n)
+    np.testing.assert_array_equal(gx[:n], np.concatenate([a[1][:h], b[1][:n - h]]))
+    np.testing.assert_array_equal(gq[:n], np.concatenate([a[2][:h], b[2][:n - h]]))
+    tol = 1e-12 if prec == B.PDFX_F64 else 2e-7
+    scale = np.abs(gv).max(axis=(1, 2), keepdims=True) + 1e-300
+    assert np.all(np.abs(a[0] + b[0] - gv) <= tol * scale)
+    if n == 63:
+        g64 = g if prec == B.PDFX_F64 else wl.GridSpec(
+            pids=g.pids, x=g.x, q2=g.q2, q_off=g.q_off, xf=g.xf.astype(np.float32).astype(np.float64))
+        wq = w_np if prec == B.PDFX_F64 else w_np.astype(np.float32).astype(np.float64)
+        loc = oracle.locate(g, x_np, q2_np)
+        ix, s, iq, inside = loc
+        rng = np.random.default_rng(75)
+        out = []
+        for _ in range(30):
+            p = int(rng.integers(0, n))
+            f = int(rng.integers(0, 11))
+            i = int(ix[p]) + int(rng.integers(-1, 3))
+            k = int(g.q_off[s[p]] + iq[p]) + int(rng.integers(-1, 3))
+            if not (0 <= i < g.xf.shape[1] and 0 <= k < g.xf.shape[2]):
+                continue
+            fd, npts = fd_knot(g64, x_np, q2_np, loc, wq[:, f], f, i, k)
+            if npts:
+                out.append((gv[f, i, k], fd))
+        arr = np.array(out)
+        assert len(arr) >= 10
+        assert metric(arr[:, 0], arr[:, 1]).max() <= TOL
