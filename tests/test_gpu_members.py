@@ -195,3 +195,20 @@ def test_large_members_split_slab(torch):
     for k, m in enumerate(mems):
         e, tol = check_member(m, out[k], x, q2, pids, "f32s")
         assert e <= tol, ("f32s", k, e, tol)
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 1025, 4097])
+def test_set_ragged_sizes(pset, members, n):
+    """Empty and ragged point counts through the one-launch set call (every
+    class of the bench set runs), each member against the oracle."""
+    x, q2 = wl.queries(8, max(n, 1))
+    x, q2 = x[:n], q2[:n]
+    pids = members[0].pids
+    for prec in ("f64", "f32s"):
+        out = pset.xfxQ2(pids, x, q2, prec=prec).double().cpu().numpy()
+        assert out.shape == (101, n, 11)
+        if n == 0:
+            continue
+        for k in range(0, 101, 10):
+            e, tol = check_member(members[k], out[k], x, q2, pids, prec)
+            assert e <= tol, (n, k, prec, e, tol)
