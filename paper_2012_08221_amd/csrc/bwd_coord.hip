@@ -211,32 +211,25 @@ __global__ __launch_bounds__(BLOCK) void coord_grad_kernel(const CoordArgs c)
                 // gathers run (every later wait for a slab copy covers them)
                 if (s == 0)
                     load_pt(p + (int64_t)gridDim.x * BLOCK, x_pt, q_pt, g_pt);
-                double du[G], dw[G];
+                // each node's flavours are contracted with dL/d(slot) first, so
+                // the two derivative stencils run once per group, not per flavour
 #pragma unroll
                 for (int jx = 0; jx < 4; ++jx) {
                     const uint4 *rowp = cur + base + jx * nq;
-                    double r[G], dr[G];
+                    double r = 0.0, dr = 0.0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         V v[G];
                         fwd::Node<V>::get(rowp + k, v);
+                        double vg = gs[s * G] * (double)v[0];
 #pragma unroll
-                        for (int g = 0; g < G; ++g) {
-                            const double vv = (double)v[g];
-                            r[g] = (k == 0) ? wq[0] * vv : fma(wq[k], vv, r[g]);
-                            dr[g] = (k == 0) ? dwq[0] * vv : fma(dwq[k], vv, dr[g]);
-                        }
+                        for (int g = 1; g < G; ++g)
+                            vg = fma(gs[s * G + g], (double)v[g], vg);
+                        r = fma(wq[k], vg, r);
+                        dr = fma(dwq[k], vg, dr);
                     }
-#pragma unroll
-                    for (int g = 0; g < G; ++g) {
-                        du[g] = (jx == 0) ? dwx[0] * r[g] : fma(dwx[jx], r[g], du[g]);
-                        dw[g] = (jx == 0) ? wx[0] * dr[g] : fma(wx[jx], dr[g], dw[g]);
-                    }
-                }
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    sx = fma(gs[s * G + g], du[g], sx);
-                    sw = fma(gs[s * G + g], dw[g], sw);
+                    sx = fma(dwx[jx], r, sx);
+                    sw = fma(wx[jx], dr, sw);
                 }
                 if (!last) {
                     fwd::wait_vm();
