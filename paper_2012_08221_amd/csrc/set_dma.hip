@@ -151,6 +151,17 @@ __device__ __forceinline__ void set_item(const SetDmaArgs &a, const SetPlan &pl,
     }
     V *out = reinterpret_cast<V *>(a.out) + (int64_t)m * a.n * n_req;
 
+    // each tile's coordinates are loaded during the first stage of the tile
+    // before (clamped to the last point), so that its location does not wait
+    // for them
+    double x_pf[PPT], q_pf[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int64_t p = t_first * tile_pts + tid + (int64_t)j * BLOCK;
+        x_pf[j] = load_point(a.x, p, a.n);
+        q_pf[j] = load_point(a.q, p, a.n);
+    }
+
     for (int64_t tile = t_first; tile < t_end; ++tile) {
         const int64_t t0 = tile * tile_pts;
         const bool more = tile + 1 < t_end;
@@ -164,8 +175,8 @@ __device__ __forceinline__ void set_item(const SetDmaArgs &a, const SetPlan &pl,
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const int64_t p = t0 + tid + (int64_t)j * BLOCK;
-            double xv = load_point(a.x, p, a.n);
-            double qv = load_point(a.q, p, a.n);
+            double xv = x_pf[j];
+            double qv = q_pf[j];
             const bool nan_in = (xv != xv) || (qv != qv);
             const bool inside = xv >= md.ax.lo && xv <= md.ax.hi && qv >= md.aq.lo &&
                                 qv <= md.aq.hi;
@@ -210,6 +221,13 @@ __device__ __forceinline__ void set_item(const SetDmaArgs &a, const SetPlan &pl,
                 if (!SPLIT && !last)
                     fwd::dma_slab<BLOCK>((s & 1) ? slab0 : slab1,
                                          gsrc + (size_t)pl.sgrp[s + 1] * gstride, chunks);
+                if (s == 0 && more)
+#pragma unroll
+                    for (int j = 0; j < PPT; ++j) {
+                        const int64_t pn = t0 + tile_pts + tid + (int64_t)j * BLOCK;
+                        x_pf[j] = load_point(a.x, pn, a.n);
+                        q_pf[j] = load_point(a.q, pn, a.n);
+                    }
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
                     V acc[G];
