@@ -202,6 +202,13 @@ __device__ __forceinline__ void set_item(const SetDmaArgs &a, const SetPlan &pl,
             if (!SPLIT)
                 base[j] += brow[j] * nq;
         }
+        if (n_stage == 0 && more)   // no stage to load the next tile's points in
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const int64_t pn = t0 + tile_pts + tid + (int64_t)j * BLOCK;
+                x_pf[j] = load_point(a.x, pn, a.n);
+                q_pf[j] = load_point(a.q, pn, a.n);
+            }
 
         fwd::wait_vm();
         __syncthreads();   // the tile's first group has landed

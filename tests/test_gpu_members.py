@@ -212,3 +212,21 @@ def test_set_ragged_sizes(pset, members, n):
         for k in range(0, 101, 10):
             e, tol = check_member(members[k], out[k], x, q2, pids, prec)
             assert e <= tol, (n, k, prec, e, tol)
+
+
+def test_set_request_the_grids_lack(torch):
+    """pids no member holds: zero columns, and the outside points still counted
+    once per member in every tile (the kernel has no flavour group to stage,
+    so each tile must still read its own points)."""
+    from paper_2012_08221_amd import api
+    members = wl.member_grids(5)
+    pset = api.PDFSet(members)
+    n = 300_001
+    x, q2 = wl.queries(9, n)
+    bad = np.arange(1000, n, 20_011)                      # outside points over many tiles
+    x[bad] = 3.0
+    pset.domain_errors()
+    for prec in ("f64", "f32s"):
+        out = pset.xfxQ2([7, 8], x, q2, prec=prec).cpu().numpy()
+        assert not out.any()
+        assert pset.domain_errors() == bad.size * len(members), prec
